@@ -1,0 +1,160 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The HIP library never loads it and
+shares no code with it.  See ``oracle.c`` for the definitions it follows.
+
+Every function here takes and returns float64 numpy arrays in the time-major
+layout ``[n_t, n_ch]``.
+
+Parity status: design, filter and STA/LTA are pinned by closed forms, brute
+force, invariants and library special cases in ``tests/test_oracle_*.py``;
+the gradient routines are pinned by finite differences, the transpose
+(dot-product) identity and an independent autodiff in
+``tests/test_oracle_grad.py``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+BTYPES = {"lowpass": 0, "highpass": 1, "bandpass": 2, "bandstop": 3}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c11",
+               "-D_DEFAULT_SOURCE", "-shared", "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        D = ctypes.POINTER(ctypes.c_double)
+        I64 = ctypes.c_int64
+        L.oracle_butter_sos.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_double, D, ctypes.POINTER(ctypes.c_int)]
+        L.oracle_butter_sos.restype = ctypes.c_int
+        for name in ("oracle_sos_filter", "oracle_sos_filter_ld"):
+            f = getattr(L, name)
+            f.argtypes = [D, ctypes.c_int, D, D, I64, I64, D]
+            f.restype = None
+        L.oracle_stalta.argtypes = [D, D, I64, I64, I64, I64, D, ctypes.POINTER(I64)]
+        L.oracle_stalta.restype = None
+        L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        _register_grad(L)
+        _lib = L
+    return _lib
+
+
+def _register_grad(L):
+    if not hasattr(L, "oracle_sos_stalta_grad"):
+        return
+    D = ctypes.POINTER(ctypes.c_double)
+    I64 = ctypes.c_int64
+    L.oracle_sos_stalta_grad.argtypes = [D, ctypes.c_int, D, D, I64, I64, I64, I64, ctypes.c_int64,
+                                         D, D, D]
+    L.oracle_sos_stalta_grad.restype = None
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().oracle_set_num_threads(int(n))
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def butter_sos(order: int, btype: str, f1: float, f2: float = 0.0, fs: float = 1.0) -> np.ndarray:
+    """Butterworth SOS by the bilinear transform; rows {b0 b1 b2 1 a1 a2}."""
+    n_max = (order + 1) // 2
+    out = np.zeros((max(1, n_max), 6), dtype=np.float64)
+    n = ctypes.c_int(0)
+    rc = lib().oracle_butter_sos(int(order), BTYPES[btype], float(f1), float(f2), float(fs), _ptr(out),
+                                 ctypes.byref(n))
+    if rc != 0:
+        raise OracleError(f"oracle_butter_sos failed with status {rc}")
+    return out[: n.value].copy()
+
+
+def sos_filter(sos, x, zi=None, extended: bool = False):
+    """Run the DF2T cascade over x [n_t, n_ch]; returns (y, zf) with zf [n_ch, n_sec, 2]."""
+    sos = _f64(sos)
+    x = _f64(x)
+    if x.ndim == 1:
+        x = x[:, None]
+    n_t, n_ch = x.shape
+    n_sec = sos.shape[0]
+    z = np.zeros((n_ch, n_sec, 2)) if zi is None else _f64(zi).copy()
+    assert z.shape == (n_ch, n_sec, 2)
+    y = np.empty_like(x)
+    f = lib().oracle_sos_filter_ld if extended else lib().oracle_sos_filter
+    f(_ptr(sos), n_sec, _ptr(x), _ptr(y), n_ch, n_t, _ptr(z))
+    return y, z
+
+
+def stalta(y, nsta: int, nlta: int, st=None, g0: int = 0):
+    """Recursive STA/LTA of y [n_t, n_ch]; returns (cf, st [n_ch, 2], g)."""
+    y = _f64(y)
+    if y.ndim == 1:
+        y = y[:, None]
+    n_t, n_ch = y.shape
+    s = np.zeros((n_ch, 2)) if st is None else _f64(st).copy()
+    cf = np.empty_like(y)
+    g = ctypes.c_int64(int(g0))
+    lib().oracle_stalta(_ptr(y), _ptr(cf), n_ch, n_t, int(nsta), int(nlta), _ptr(s), ctypes.byref(g))
+    return cf, s, int(g.value)
+
+
+def window_samples(seconds: float, fs: float) -> int:
+    """Window length in samples: round(T * fs) (reading R4)."""
+    return int(round(seconds * fs))
+
+
+class Stream:
+    """Chunked SOS + STA/LTA with carried state, the oracle's process(chunk, state)."""
+
+    def __init__(self, sos, n_ch: int, nsta: int | None = None, nlta: int | None = None):
+        self.sos = _f64(sos)
+        self.n_ch = n_ch
+        self.zi = np.zeros((n_ch, self.sos.shape[0], 2))
+        self.nsta, self.nlta = nsta, nlta
+        self.st = np.zeros((n_ch, 2))
+        self.g = 0
+
+    def process(self, x):
+        y, self.zi = sos_filter(self.sos, x, self.zi)
+        if self.nsta is None:
+            return y, None
+        cf, self.st, self.g = stalta(y, self.nsta, self.nlta, self.st, self.g)
+        return y, cf

@@ -1,0 +1,371 @@
+/*
+ * FP64 CPU oracle for the stateful chunked SOS + STA/LTA path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path may call, link or
+ * load this file: only the tests, the smoke check and the benchmark's CPU
+ * baseline use it.  It shares no code, header, table or helper with the HIP
+ * library; its own design, filter, STA/LTA and gradient routines are written
+ * out from their textbook definitions, one plain loop at a time.
+ *
+ * What it computes (the paper, Section 3.4 "Signal processing, pipelines,
+ * and algorithm integration", and its performance Section 5.2):
+ *   - stateful-compatible causal IIR filtering in second-order sections: a
+ *     chunk goes in, an output of the same length comes out and the filter
+ *     state is carried to the next call, so that a chunked run equals a
+ *     one-shot run (Section 3.4; Table 1 "IIR ... SOS" row);
+ *   - bandpass / lowpass / highpass wrappers (Section 3.4), designed here as
+ *     Butterworth filters by the bilinear transform with pre-warping;
+ *   - a threshold energy-detector characteristic (Section 3.4, monitors),
+ *     taken as the recursive STA/LTA ratio on the squared filter output.
+ * The paper gives no formula for any of these; the readings are the textbook
+ * ones (Oppenheim & Schafer for the bilinear Butterworth design and the
+ * direct-form-II-transposed section; the exponential recursive STA/LTA) and
+ * are listed, with every other reading, in the design notes.
+ *
+ * Layout: records are time-major x[t * n_ch + c] (channel contiguous), the
+ * paper's 'nt_nc' tape convention (Section 3.6).  Arithmetic is IEEE double,
+ * built without fast-math and without FMA contraction.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL 1
+#define ORC_EUNSTABLE 5
+
+enum { ORC_LOWPASS = 0, ORC_HIGHPASS = 1, ORC_BANDPASS = 2, ORC_BANDSTOP = 3 };
+
+typedef double complex cplx;
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------------
+ * Butterworth design by the bilinear transform (textbook; paper silent).
+ *   1. analog prototype poles p_k = exp(j pi (2k + N + 1) / (2N)), gain 1;
+ *   2. pre-warp each band edge: W = 2 fs tan(pi f / fs);
+ *   3. frequency transform (LP, HP, BP, BS);
+ *   4. bilinear map z = (2 fs + s) / (2 fs - s), missing zeros go to z = -1;
+ *   5. pair poles and zeros into sections.
+ * ---------------------------------------------------------------------- */
+
+static cplx prod_minus(const cplx *r, int n) {  /* prod(-r_i) */
+  cplx a = 1.0;
+  for (int i = 0; i < n; ++i) a *= -r[i];
+  return a;
+}
+
+/* Analog zeros/poles/gain of the transformed prototype. Arrays hold up to 2N. */
+static int analog_zpk(int N, int btype, double w1, double w2,
+                      cplx *z, int *nz, cplx *p, int *np, double *k) {
+  cplx proto[256];
+  for (int i = 0; i < N; ++i) proto[i] = cexp(I * M_PI * (2.0 * i + N + 1.0) / (2.0 * N));
+  *nz = 0;
+  *np = 0;
+  if (btype == ORC_LOWPASS) {
+    for (int i = 0; i < N; ++i) p[(*np)++] = w1 * proto[i];
+    *k = pow(w1, N);
+  } else if (btype == ORC_HIGHPASS) {
+    for (int i = 0; i < N; ++i) p[(*np)++] = w1 / proto[i];
+    for (int i = 0; i < N; ++i) z[(*nz)++] = 0.0;
+    *k = creal(1.0 / prod_minus(proto, N));
+  } else if (btype == ORC_BANDPASS) {
+    double w0sq = w1 * w2, bw = w2 - w1;
+    for (int i = 0; i < N; ++i) {
+      cplx a = proto[i] * bw / 2.0;
+      cplx r = csqrt(a * a - w0sq);
+      p[(*np)++] = a + r;
+      p[(*np)++] = a - r;
+    }
+    for (int i = 0; i < N; ++i) z[(*nz)++] = 0.0;
+    *k = pow(bw, N);
+  } else if (btype == ORC_BANDSTOP) {
+    double w0sq = w1 * w2, bw = w2 - w1, w0 = sqrt(w0sq);
+    for (int i = 0; i < N; ++i) {
+      cplx a = (bw / 2.0) / proto[i];
+      cplx r = csqrt(a * a - w0sq);
+      p[(*np)++] = a + r;
+      p[(*np)++] = a - r;
+    }
+    for (int i = 0; i < N; ++i) {
+      z[(*nz)++] = I * w0;
+      z[(*nz)++] = -I * w0;
+    }
+    /* H(s) = 1/prod(s' - p) with s' = B s / (s^2 + W0^2) gives gain 1/prod(-p) */
+    *k = creal(1.0 / prod_minus(proto, N));
+  } else {
+    return ORC_EINVAL;
+  }
+  return ORC_OK;
+}
+
+static int is_real(cplx v) { return fabs(cimag(v)) <= 1e-10 * (1.0 + cabs(v)); }
+
+/* Pair poles/zeros into sections (reading R7): the pole closest to the unit
+ * circle goes into the LAST remaining section, with its conjugate (or, for a
+ * real pole, the next real pole closest to the circle), and with the zeros
+ * nearest to it; sections therefore run from the best-damped to the
+ * least-damped pole pair.  The overall gain multiplies section 1's
+ * numerator. */
+static int zpk_to_sos(const cplx *z, int nz, const cplx *p, int np, double k,
+                      double *sos, int *n_sec_out) {
+  int n_sec = (np + 1) / 2;
+  int used_p[512], used_z[512];
+  memset(used_p, 0, sizeof used_p);
+  memset(used_z, 0, sizeof used_z);
+  for (int s = n_sec - 1; s >= 0; --s) {
+    int i1 = -1;
+    for (int i = 0; i < np; ++i) {
+      if (used_p[i]) continue;
+      if (i1 < 0 || cabs(p[i]) > cabs(p[i1]) ||
+          (cabs(p[i]) == cabs(p[i1]) && cimag(p[i]) > cimag(p[i1])))
+        i1 = i;
+    }
+    used_p[i1] = 1;
+    int i2 = -1;
+    if (!is_real(p[i1])) {
+      for (int i = 0; i < np; ++i) {
+        if (used_p[i]) continue;
+        if (i2 < 0 || cabs(p[i] - conj(p[i1])) < cabs(p[i2] - conj(p[i1]))) i2 = i;
+      }
+    } else {
+      for (int i = 0; i < np; ++i) {
+        if (used_p[i] || !is_real(p[i])) continue;
+        if (i2 < 0 || cabs(p[i]) > cabs(p[i2])) i2 = i;
+      }
+    }
+    if (i2 >= 0) used_p[i2] = 1;
+    int n_poles = (i2 >= 0) ? 2 : 1;
+
+    int j1 = -1, j2 = -1;
+    if (n_poles == 2) {
+      for (int j = 0; j < nz; ++j) {
+        if (used_z[j]) continue;
+        if (j1 < 0 || cabs(z[j] - p[i1]) < cabs(z[j1] - p[i1])) j1 = j;
+      }
+      if (j1 >= 0) {
+        used_z[j1] = 1;
+        if (!is_real(z[j1])) {
+          for (int j = 0; j < nz; ++j) {
+            if (used_z[j]) continue;
+            if (j2 < 0 || cabs(z[j] - conj(z[j1])) < cabs(z[j2] - conj(z[j1]))) j2 = j;
+          }
+        } else {
+          for (int j = 0; j < nz; ++j) {
+            if (used_z[j] || !is_real(z[j])) continue;
+            if (j2 < 0 || cabs(z[j] - p[i1]) < cabs(z[j2] - p[i1])) j2 = j;
+          }
+        }
+        if (j2 >= 0) used_z[j2] = 1;
+      }
+    } else {
+      for (int j = 0; j < nz; ++j) {
+        if (used_z[j] || !is_real(z[j])) continue;
+        if (j1 < 0 || cabs(z[j] - p[i1]) < cabs(z[j1] - p[i1])) j1 = j;
+      }
+      if (j1 >= 0) used_z[j1] = 1;
+    }
+
+    double *row = sos + 6 * s;
+    /* numerator: prod (1 - z_i q^-1) over this section's zeros */
+    if (j1 >= 0 && j2 >= 0) {
+      row[0] = 1.0;
+      row[1] = -creal(z[j1] + z[j2]);
+      row[2] = creal(z[j1] * z[j2]);
+    } else if (j1 >= 0) {
+      row[0] = 1.0;
+      row[1] = -creal(z[j1]);
+      row[2] = 0.0;
+    } else {
+      row[0] = 1.0;
+      row[1] = 0.0;
+      row[2] = 0.0;
+    }
+    row[3] = 1.0;
+    if (n_poles == 2) {
+      row[4] = -creal(p[i1] + p[i2]);
+      row[5] = creal(p[i1] * p[i2]);
+    } else {
+      row[4] = -creal(p[i1]);
+      row[5] = 0.0;
+    }
+  }
+  sos[0] *= k;
+  sos[1] *= k;
+  sos[2] *= k;
+  *n_sec_out = n_sec;
+  return ORC_OK;
+}
+
+/* order = total digital order (bandpass / bandstop: even, N = order / 2).
+ * btype: 0 lowpass (f1), 1 highpass (f1), 2 bandpass (f1, f2), 3 bandstop.
+ * sos_out: caller-owned [ceil(order/2)][6] rows {b0 b1 b2 1 a1 a2}. */
+int oracle_butter_sos(int order, int btype, double f1, double f2, double fs,
+                      double *sos_out, int *n_sec) {
+  if (!sos_out || !n_sec || !(fs > 0.0) || order < 1 || order > 128) return ORC_EINVAL;
+  double nyq = fs / 2.0;
+  int N;
+  if (btype == ORC_LOWPASS || btype == ORC_HIGHPASS) {
+    if (!(f1 > 0.0 && f1 < nyq)) return ORC_EINVAL;
+    N = order;
+  } else if (btype == ORC_BANDPASS || btype == ORC_BANDSTOP) {
+    if (order % 2 != 0) return ORC_EINVAL;
+    if (!(f1 > 0.0 && f1 < f2 && f2 < nyq)) return ORC_EINVAL;
+    N = order / 2;
+  } else {
+    return ORC_EINVAL;
+  }
+  double fs2 = 2.0 * fs;
+  double w1 = fs2 * tan(M_PI * f1 / fs);
+  double w2 = (btype >= ORC_BANDPASS) ? fs2 * tan(M_PI * f2 / fs) : 0.0;
+
+  cplx za[256], pa[256];
+  int nz, np;
+  double k;
+  int rc = analog_zpk(N, btype, w1, w2, za, &nz, pa, &np, &k);
+  if (rc) return rc;
+
+  /* bilinear transform */
+  cplx zd[256], pd[256];
+  cplx num = 1.0, den = 1.0;
+  for (int i = 0; i < nz; ++i) {
+    zd[i] = (fs2 + za[i]) / (fs2 - za[i]);
+    num *= (fs2 - za[i]);
+  }
+  for (int i = 0; i < np; ++i) {
+    pd[i] = (fs2 + pa[i]) / (fs2 - pa[i]);
+    den *= (fs2 - pa[i]);
+  }
+  int nzd = nz;
+  for (int i = nz; i < np; ++i) zd[nzd++] = -1.0;
+  double kd = k * creal(num / den);
+  for (int i = 0; i < np; ++i)
+    if (!(cabs(pd[i]) < 1.0)) return ORC_EUNSTABLE;
+  return zpk_to_sos(zd, nzd, pd, np, kd, sos_out, n_sec);
+}
+
+/* ------------------------------------------------------------------------
+ * Direct-form-II-transposed cascade (reading of the stateful IIR-SOS
+ * operator, Section 3.4).  For each channel and sample, with v the input of
+ * section k:
+ *     y  = b0 v + z1
+ *     z1 = b1 v - a1 y + z2
+ *     z2 = b2 v - a2 y
+ * and y becomes the input of section k + 1.  zi[c][k][0..1] = (z1, z2) is read
+ * at entry and written back at exit, so consecutive calls continue the
+ * recurrence exactly (chunked == one-shot, bit for bit).
+ * Rows of sos are {b0 b1 b2 a0 a1 a2}; they are divided by a0.
+ * x and y may be the same array.
+ * ---------------------------------------------------------------------- */
+void oracle_sos_filter(const double *sos, int n_sec, const double *x, double *y,
+                       int64_t n_ch, int64_t n_t, double *zi) {
+  const int64_t CB = 8;  /* channels per task: one cache line of doubles */
+  int64_t n_blk = (n_ch + CB - 1) / CB;
+#pragma omp parallel for schedule(static)
+  for (int64_t blk = 0; blk < n_blk; ++blk) {
+    int64_t c0 = blk * CB, c1 = c0 + CB < n_ch ? c0 + CB : n_ch;
+    for (int64_t t = 0; t < n_t; ++t) {
+      for (int64_t c = c0; c < c1; ++c) {
+        double v = x[t * n_ch + c];
+        for (int s = 0; s < n_sec; ++s) {
+          const double *r = sos + 6 * s;
+          double a0 = r[3];
+          double b0 = r[0] / a0, b1 = r[1] / a0, b2 = r[2] / a0;
+          double a1 = r[4] / a0, a2 = r[5] / a0;
+          double *z = zi + (c * n_sec + s) * 2;
+          double out = b0 * v + z[0];
+          z[0] = b1 * v - a1 * out + z[1];
+          z[1] = b2 * v - a2 * out;
+          v = out;
+        }
+        y[t * n_ch + c] = v;
+      }
+    }
+  }
+}
+
+/* The same loop in x87 extended precision (64-bit significand), used only to
+ * bound the double-precision oracle's own rounding error in the tests. */
+void oracle_sos_filter_ld(const double *sos, int n_sec, const double *x, double *y,
+                          int64_t n_ch, int64_t n_t, double *zi) {
+  for (int64_t c = 0; c < n_ch; ++c) {
+    long double z[2 * 128];
+    for (int s = 0; s < n_sec; ++s) {
+      z[2 * s] = zi[(c * n_sec + s) * 2];
+      z[2 * s + 1] = zi[(c * n_sec + s) * 2 + 1];
+    }
+    for (int64_t t = 0; t < n_t; ++t) {
+      long double v = x[t * n_ch + c];
+      for (int s = 0; s < n_sec; ++s) {
+        const double *r = sos + 6 * s;
+        long double a0 = r[3];
+        long double b0 = r[0] / a0, b1 = r[1] / a0, b2 = r[2] / a0;
+        long double a1 = r[4] / a0, a2 = r[5] / a0;
+        long double out = b0 * v + z[2 * s];
+        z[2 * s] = b1 * v - a1 * out + z[2 * s + 1];
+        z[2 * s + 1] = b2 * v - a2 * out;
+        v = out;
+      }
+      y[t * n_ch + c] = (double)v;
+    }
+    for (int s = 0; s < n_sec; ++s) {
+      zi[(c * n_sec + s) * 2] = (double)z[2 * s];
+      zi[(c * n_sec + s) * 2 + 1] = (double)z[2 * s + 1];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Recursive STA/LTA characteristic function (reading: the exponential
+ * recursive energy ratio; the paper names threshold energy detectors as
+ * monitors, Section 3.4).  With e = y^2, cs = 1/nsta, cl = 1/nlta:
+ *     sta = (1 - cs) sta + cs e
+ *     lta = (1 - cl) lta + cl e
+ *     cf  = sta / lta   if g >= nlta and lta > 0, else 0
+ * where g is the 0-based global index of the sample since the state was
+ * zeroed.  st[c][0..1] = (sta, lta) and *g0 (the index of this call's first
+ * sample) are read at entry and advanced at exit.
+ * ---------------------------------------------------------------------- */
+void oracle_stalta(const double *y, double *cf, int64_t n_ch, int64_t n_t,
+                   int64_t nsta, int64_t nlta, double *st, int64_t *g0) {
+  const double cs = 1.0 / (double)nsta, cl = 1.0 / (double)nlta;
+  const int64_t CB = 8;
+  int64_t n_blk = (n_ch + CB - 1) / CB;
+  int64_t gstart = *g0;
+#pragma omp parallel for schedule(static)
+  for (int64_t blk = 0; blk < n_blk; ++blk) {
+    int64_t c0 = blk * CB, c1 = c0 + CB < n_ch ? c0 + CB : n_ch;
+    for (int64_t t = 0; t < n_t; ++t) {
+      for (int64_t c = c0; c < c1; ++c) {
+        double v = y[t * n_ch + c];
+        double e = v * v;
+        double sta = (1.0 - cs) * st[2 * c] + cs * e;
+        double lta = (1.0 - cl) * st[2 * c + 1] + cl * e;
+        st[2 * c] = sta;
+        st[2 * c + 1] = lta;
+        cf[t * n_ch + c] = (gstart + t >= nlta && lta > 0.0) ? sta / lta : 0.0;
+      }
+    }
+  }
+  *g0 = gstart + n_t;
+}
