@@ -1,0 +1,182 @@
+/*
+ * filark.h - C ABI of the MI355X stateful chunked SOS + STA/LTA library.
+ *
+ * The operators follow the paper's stateful-compatible contract (FiLark,
+ * Section 3.4 "Signal processing, pipelines, and algorithm integration"):
+ * a call takes one chunk of a channel x time stream, returns an output of the
+ * same length and carries the operator state to the next call, so that any
+ * split of a record into chunks gives the output of a single call over the
+ * whole record.  The first chunk after initialisation carries the start-up
+ * transient set by the zero initial condition; later chunks carry none
+ * (Section 5.2, "Signal processing performance").
+ *
+ * Data layout (every entry point): records are FP32, time-major
+ * [n_t][n_ch] with row stride n_ch (channel contiguous), the 'nt_nc'
+ * convention of the paper's binary tape (Section 3.6).
+ *
+ * Ownership: the caller owns every data buffer (device memory for signals,
+ * host memory for coefficients and state snapshots).  The library owns its
+ * state objects, their device state and scan tables, and frees them in the
+ * matching *_destroy call.
+ *
+ * Errors: every call returns a filark_status; nothing aborts or throws across
+ * the ABI.  filark_last_error() gives a thread-local message for the last
+ * failure on the calling thread.  Argument errors are detected on the host
+ * before anything is enqueued.
+ *
+ * Asynchrony: *_process calls only enqueue work on `stream` (a hipStream_t;
+ * NULL is the null stream) and return; the caller synchronises before reading
+ * outputs.  Calls that use one state object must be issued in order on one
+ * stream: the state is a sequential dependency.  filark_state_get/_set and
+ * filark_check synchronise `stream` themselves.
+ */
+#ifndef FILARK_H
+#define FILARK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum filark_status {
+  FILARK_OK = 0,
+  FILARK_EINVAL = 1,     /* bad argument (range, null pointer, aliasing) */
+  FILARK_ESHAPE = 2,     /* n_ch differs from the one the state was made for */
+  FILARK_ENOMEM = 3,     /* host or device allocation failed */
+  FILARK_EHIP = 4,       /* a HIP runtime call failed (message has details) */
+  FILARK_EUNSTABLE = 5,  /* a pole on or outside the unit circle */
+  FILARK_ETIMEOUT = 6    /* a kernel's bounded wait expired (results invalid) */
+} filark_status;
+
+typedef enum filark_btype {
+  FILARK_LOWPASS = 0,
+  FILARK_HIGHPASS = 1,
+  FILARK_BANDPASS = 2,
+  FILARK_BANDSTOP = 3
+} filark_btype;
+
+/* State kinds for filark_state_get / filark_state_set. */
+enum { FILARK_STATE_SOS = 0, FILARK_STATE_STALTA = 1 };
+
+typedef struct filark_sos_state *filark_sos_t;
+typedef struct filark_stalta_state *filark_stalta_t;
+
+/*
+ * Butterworth design by the bilinear transform with pre-warped band edges
+ * (the paper's bandpass / lowpass / highpass wrappers of the real-time IIR,
+ * Section 3.4; the design method is the textbook one, the paper gives none).
+ *   order  total digital order; for FILARK_BANDPASS / FILARK_BANDSTOP it must
+ *          be even (prototype order order/2).  1 <= order <= 64.
+ *   btype  a filark_btype.  LP/HP use f1; BP/BS use f1 < f2.
+ *   f1,f2  band edges in Hz, 0 < f < fs/2.   fs: sample rate in Hz.
+ *   sos_out caller-owned host array of ceil(order/2) rows of 6 doubles
+ *          {b0, b1, b2, 1, a1, a2}; sections run from the best-damped pole
+ *          pair to the one closest to the unit circle; the overall gain sits
+ *          in section 1's numerator.
+ *   n_sec  receives ceil(order/2).
+ * Host only, synchronous.  FILARK_EINVAL on a bad argument,
+ * FILARK_EUNSTABLE if a designed pole has |p| >= 1 (numerically).
+ */
+filark_status filark_sos_design(int order, int btype, double f1, double f2, double fs,
+                                double *sos_out, int *n_sec);
+
+/*
+ * Create a stateful SOS cascade for n_ch channels (Section 3.4, Table 1
+ * "IIR (offline & realtime SOS)", stateful and GPU columns).
+ *   sos    host array [n_sec][6] {b0 b1 b2 a0 a1 a2}; rows are normalised by
+ *          a0 (which must be nonzero).  1 <= n_sec <= 8.  Copied.
+ *   n_ch   channels, >= 1.
+ *   flags  0 (reserved).
+ * Allocates and zeroes the device state (zero initial condition) and uploads
+ * the FP64 scan tables.  Runs on the current HIP device; `stream` orders the
+ * upload.  FILARK_EUNSTABLE if a section has a pole with |p| >= 1.
+ */
+filark_status filark_sos_init(filark_sos_t *st, const double *sos, int n_sec, int64_t n_ch,
+                              unsigned flags, hipStream_t stream);
+
+/*
+ * Filter one chunk: out = SOS(in) with the state carried in and out
+ * (process(chunk, state) -> (output, new_state), Section 3.4).
+ *   in, out  device FP32 [n_t][n_ch]; out == in is allowed (in place).
+ *   n_ch     must equal the n_ch given to filark_sos_init (else FILARK_ESHAPE).
+ *   n_t      samples in this chunk, 0 <= n_t <= 2^31 - 1; 0 is a no-op.
+ * Asynchronous on `stream`.
+ */
+filark_status filark_sos_process(filark_sos_t st, const float *in, float *out, int64_t n_ch,
+                                 int64_t n_t, hipStream_t stream);
+
+/*
+ * Create a recursive STA/LTA characteristic-function state for n_ch channels
+ * (energy-detector monitor, Section 3.4).  nsta = round(sta_s * fs),
+ * nlta = round(lta_s * fs), both >= 1.  With e = y^2:
+ *   sta <- (1 - 1/nsta) sta + e / nsta,   lta <- (1 - 1/nlta) lta + e / nlta,
+ *   cf = sta / lta once the global sample index reaches nlta and lta > 0,
+ *   else 0.  The state (sta, lta, sample counter) starts at zero.
+ */
+filark_status filark_stalta_init(filark_stalta_t *st, double sta_s, double lta_s, double fs,
+                                 int64_t n_ch, hipStream_t stream);
+
+/*
+ * STA/LTA of one chunk of an already filtered signal.
+ *   in  device FP32 [n_t][n_ch];  cf  device FP32 [n_t][n_ch] (may equal in).
+ * Asynchronous on `stream`.
+ */
+filark_status filark_stalta_process(filark_stalta_t st, const float *in, float *cf, int64_t n_ch,
+                                    int64_t n_t, hipStream_t stream);
+
+/*
+ * Fused chunk: y = SOS(in), cf = STA/LTA(y), both states carried.  Equivalent
+ * to filark_sos_process followed by filark_stalta_process on its output, in
+ * one pass over HBM.
+ *   y_or_null  device FP32 [n_t][n_ch] or NULL (then y is not written);
+ *              may equal in.
+ *   cf         device FP32 [n_t][n_ch]; must differ from y_or_null.
+ * Both states must be for n_ch channels.  Asynchronous on `stream`.
+ */
+filark_status filark_sos_stalta_process(filark_sos_t sos, filark_stalta_t sl, const float *in,
+                                        float *y_or_null, float *cf, int64_t n_ch, int64_t n_t,
+                                        hipStream_t stream);
+
+/*
+ * Snapshot / restore a state in a canonical FP64 host layout, independent of
+ * the device realisation:
+ *   FILARK_STATE_SOS:    [n_ch][n_sec][2] doubles, the direct-form-II-
+ *                        transposed delay pair (z1, z2) of each section;
+ *                        bytes = n_ch * n_sec * 16.
+ *   FILARK_STATE_STALTA: [n_ch][2] doubles (sta, lta) followed by one
+ *                        int64 global sample counter; bytes = n_ch * 16 + 8.
+ * `st` is a filark_sos_t or filark_stalta_t matching `kind`.  Both calls
+ * synchronise `stream` (the state is read or written after all work already
+ * enqueued on it).  FILARK_EINVAL if bytes does not match.
+ */
+filark_status filark_state_get(const void *st, int kind, void *host_buf, size_t bytes,
+                               hipStream_t stream);
+filark_status filark_state_set(void *st, int kind, const void *host_buf, size_t bytes,
+                               hipStream_t stream);
+
+/*
+ * Synchronise `stream` and report whether any kernel that ran on `st`
+ * (kind as above) hit its bounded-wait limit (FILARK_ETIMEOUT; the outputs of
+ * that call are then invalid).  Clears the flag.
+ */
+filark_status filark_check(const void *st, int kind, hipStream_t stream);
+
+/* Free a state object and its device memory (NULL is a no-op). */
+filark_status filark_sos_destroy(filark_sos_t st);
+filark_status filark_stalta_destroy(filark_stalta_t st);
+
+/* Thread-local message describing the last failure on this thread ("" if none). */
+const char *filark_last_error(void);
+
+/* Library version string. */
+const char *filark_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FILARK_H */

@@ -1,0 +1,228 @@
+"""Python binding of libfilark (stateful chunked SOS + STA/LTA on MI355X).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libfilark.so``; PyTorch supplies device memory and streams.  There is no
+CPU fallback: if the library is missing or a call fails, an exception is
+raised.
+
+Layout: FP32 CUDA tensors of shape ``[n_t, n_ch]`` (time-major, channel
+contiguous).  Calls are asynchronous on the given (default: current) stream.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfilark.so")
+
+OK, EINVAL, ESHAPE, ENOMEM, EHIP, EUNSTABLE, ETIMEOUT = range(7)
+BTYPES = {"lowpass": 0, "highpass": 1, "bandpass": 2, "bandstop": 3}
+STATE_SOS, STATE_STALTA = 0, 1
+
+_lib = None
+
+# Every symbol the C header declares; checked on load.
+EXPORTS = (
+    "filark_sos_design", "filark_sos_init", "filark_sos_process", "filark_stalta_init",
+    "filark_stalta_process", "filark_sos_stalta_process", "filark_state_get", "filark_state_set",
+    "filark_check", "filark_sos_destroy", "filark_stalta_destroy", "filark_last_error",
+    "filark_version",
+)
+
+
+class FilarkError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"filark status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libfilark.so (built in-tree by ``paper_2605_20132_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FilarkError(EHIP, f"{LIB_PATH} is missing; build it with python -m paper_2605_20132_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    for name in EXPORTS:
+        if not hasattr(L, name):
+            raise FilarkError(EHIP, f"libfilark.so does not export {name}")
+    D = ctypes.POINTER(ctypes.c_double)
+    vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    L.filark_sos_design.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, D, ctypes.POINTER(ctypes.c_int)]
+    L.filark_sos_init.argtypes = [ctypes.POINTER(vp), D, ctypes.c_int, i64, ctypes.c_uint, vp]
+    L.filark_sos_process.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.filark_stalta_init.argtypes = [ctypes.POINTER(vp), ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     i64, vp]
+    L.filark_stalta_process.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.filark_sos_stalta_process.argtypes = [vp, vp, vp, vp, vp, i64, i64, vp]
+    L.filark_state_get.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
+    L.filark_state_set.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
+    L.filark_check.argtypes = [vp, ctypes.c_int, vp]
+    L.filark_sos_destroy.argtypes = [vp]
+    L.filark_stalta_destroy.argtypes = [vp]
+    for name in EXPORTS:
+        if name not in ("filark_last_error", "filark_version"):
+            getattr(L, name).restype = st
+    L.filark_last_error.restype = ctypes.c_char_p
+    L.filark_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise FilarkError(rc, lib().filark_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev_f32(t, name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2 \
+            or not t.is_contiguous():
+        raise FilarkError(EINVAL, f"{name} must be a contiguous float32 CUDA tensor [n_t, n_ch]")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def version() -> str:
+    return lib().filark_version().decode()
+
+
+def sos_design(order: int, btype: str, f1: float, f2: float = 0.0, fs: float = 1.0) -> np.ndarray:
+    """Butterworth SOS by the bilinear transform, rows {b0 b1 b2 1 a1 a2}."""
+    n_max = max(1, (int(order) + 1) // 2)
+    out = np.zeros((n_max, 6), dtype=np.float64)
+    n = ctypes.c_int(0)
+    _check(lib().filark_sos_design(int(order), BTYPES[btype], float(f1), float(f2), float(fs),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(n)))
+    return out[: n.value].copy()
+
+
+class SOSState:
+    """Stateful SOS cascade for ``n_ch`` channels (zero initial condition)."""
+
+    def __init__(self, sos, n_ch: int, stream=None):
+        self._h = ctypes.c_void_p()
+        self.sos = np.ascontiguousarray(np.asarray(sos, dtype=np.float64))
+        if self.sos.ndim != 2 or self.sos.shape[1] != 6:
+            raise FilarkError(EINVAL, "sos must have shape [n_sec, 6]")
+        self.n_ch = int(n_ch)
+        self.n_sec = self.sos.shape[0]
+        _check(lib().filark_sos_init(ctypes.byref(self._h),
+                                     self.sos.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     self.n_sec, self.n_ch, 0, _stream(stream)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def process(self, x, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().filark_sos_process(self._h, _dev_f32(x, "x"), _dev_f32(out, "out"), x.shape[1],
+                                        x.shape[0], _stream(stream)))
+        return out
+
+    def get_state(self, stream=None) -> np.ndarray:
+        buf = np.empty((self.n_ch, self.n_sec, 2), dtype=np.float64)
+        _check(lib().filark_state_get(self._h, STATE_SOS, buf.ctypes.data, buf.nbytes, _stream(stream)))
+        return buf
+
+    def set_state(self, z, stream=None):
+        buf = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+        _check(lib().filark_state_set(self._h, STATE_SOS, buf.ctypes.data, buf.nbytes, _stream(stream)))
+
+    def check(self, stream=None):
+        _check(lib().filark_check(self._h, STATE_SOS, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().filark_sos_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class StaLtaState:
+    """Recursive STA/LTA state (windows in seconds, rounded to samples)."""
+
+    def __init__(self, sta_s: float, lta_s: float, fs: float, n_ch: int, stream=None):
+        self._h = ctypes.c_void_p()
+        self.n_ch = int(n_ch)
+        self.nsta = int(round(sta_s * fs))
+        self.nlta = int(round(lta_s * fs))
+        _check(lib().filark_stalta_init(ctypes.byref(self._h), float(sta_s), float(lta_s), float(fs),
+                                        self.n_ch, _stream(stream)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def process(self, y, cf=None, stream=None):
+        import torch
+
+        if cf is None:
+            cf = torch.empty_like(y)
+        _check(lib().filark_stalta_process(self._h, _dev_f32(y, "y"), _dev_f32(cf, "cf"), y.shape[1],
+                                           y.shape[0], _stream(stream)))
+        return cf
+
+    def get_state(self, stream=None):
+        buf = np.empty(self.n_ch * 2 + 1, dtype=np.float64)
+        _check(lib().filark_state_get(self._h, STATE_STALTA, buf.ctypes.data, buf.nbytes, _stream(stream)))
+        counter = int(buf[-1:].view(np.int64)[0])
+        return buf[:-1].reshape(self.n_ch, 2).copy(), counter
+
+    def set_state(self, st, counter: int, stream=None):
+        buf = np.empty(self.n_ch * 2 + 1, dtype=np.float64)
+        buf[:-1] = np.asarray(st, dtype=np.float64).reshape(-1)
+        buf[-1:] = np.array([int(counter)], dtype=np.int64).view(np.float64)
+        _check(lib().filark_state_set(self._h, STATE_STALTA, buf.ctypes.data, buf.nbytes, _stream(stream)))
+
+    def check(self, stream=None):
+        _check(lib().filark_check(self._h, STATE_STALTA, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().filark_stalta_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sos_stalta_process(sos: SOSState, sl: StaLtaState, x, y=None, cf=None, write_y: bool = True,
+                       stream=None):
+    """Fused chunk: y = SOS(x), cf = STA/LTA(y).  Returns (y or None, cf)."""
+    import torch
+
+    if cf is None:
+        cf = torch.empty_like(x)
+    if write_y and y is None:
+        y = torch.empty_like(x)
+    yp = _dev_f32(y, "y") if (write_y and y is not None) else ctypes.c_void_p(0)
+    _check(lib().filark_sos_stalta_process(sos.handle, sl.handle, _dev_f32(x, "x"), yp, _dev_f32(cf, "cf"),
+                                           x.shape[1], x.shape[0], _stream(stream)))
+    return (y if write_y else None), cf
