@@ -159,6 +159,17 @@ filark_status filark_state_set(void *st, int kind, const void *host_buf, size_t 
                                hipStream_t stream);
 
 /*
+ * Tile shape of a state object's kernels (a tuning knob; results do not
+ * depend on it beyond FP64 rounding of the carries): `block` samples per lane
+ * (32 or 64) and `waves` data waves per workgroup (1 .. 8), i.e. time
+ * segments of block * waves samples.  Default 64 x 3.  Both states passed to
+ * filark_sos_stalta_process must have the same shape.  _set synchronises
+ * `stream` and rebuilds the scan tables; kind as for filark_state_get.
+ */
+filark_status filark_tile_set(void *st, int kind, int block, int waves, hipStream_t stream);
+filark_status filark_tile_get(const void *st, int kind, int *block, int *waves);
+
+/*
  * Synchronise `stream` and report whether any kernel that ran on `st`
  * (kind as above) hit its bounded-wait limit (FILARK_ETIMEOUT; the outputs of
  * that call are then invalid).  Clears the flag.

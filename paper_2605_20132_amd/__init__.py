@@ -30,7 +30,7 @@ EXPORTS = (
     "filark_sos_design", "filark_sos_init", "filark_sos_process", "filark_stalta_init",
     "filark_stalta_process", "filark_sos_stalta_process", "filark_state_get", "filark_state_set",
     "filark_check", "filark_sos_destroy", "filark_stalta_destroy", "filark_last_error",
-    "filark_version",
+    "filark_version", "filark_tile_set", "filark_tile_get",
 )
 
 
@@ -64,6 +64,8 @@ def lib():
     L.filark_state_get.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
     L.filark_state_set.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
     L.filark_check.argtypes = [vp, ctypes.c_int, vp]
+    L.filark_tile_set.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.filark_tile_get.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.filark_sos_destroy.argtypes = [vp]
     L.filark_stalta_destroy.argtypes = [vp]
     for name in EXPORTS:
@@ -150,6 +152,14 @@ class SOSState:
     def check(self, stream=None):
         _check(lib().filark_check(self._h, STATE_SOS, _stream(stream)))
 
+    def set_tile(self, block: int, waves: int, stream=None):
+        _check(lib().filark_tile_set(self._h, STATE_SOS, int(block), int(waves), _stream(stream)))
+
+    def tile(self):
+        b, w = ctypes.c_int(), ctypes.c_int()
+        _check(lib().filark_tile_get(self._h, STATE_SOS, ctypes.byref(b), ctypes.byref(w)))
+        return b.value, w.value
+
     def close(self):
         if self._h:
             lib().filark_sos_destroy(self._h)
@@ -200,6 +210,14 @@ class StaLtaState:
 
     def check(self, stream=None):
         _check(lib().filark_check(self._h, STATE_STALTA, _stream(stream)))
+
+    def set_tile(self, block: int, waves: int, stream=None):
+        _check(lib().filark_tile_set(self._h, STATE_STALTA, int(block), int(waves), _stream(stream)))
+
+    def tile(self):
+        b, w = ctypes.c_int(), ctypes.c_int()
+        _check(lib().filark_tile_get(self._h, STATE_STALTA, ctypes.byref(b), ctypes.byref(w)))
+        return b.value, w.value
 
     def close(self):
         if self._h:

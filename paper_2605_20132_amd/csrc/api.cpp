@@ -51,7 +51,8 @@ filark_status fail(filark_status st, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(FILARK_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kDefaultWaves = 4;
+constexpr int kDefaultWaves = 3;
+constexpr int kDefaultBlock = 64;
 constexpr int kSpinLimit = 1 << 22;
 
 // Dense row-major n x n matrices in FP64.
@@ -167,6 +168,7 @@ struct filark_sos_state {
   int64_t n_ch = 0;
   Cascade cas;
   int waves = kDefaultWaves;
+  int block = kDefaultBlock;
   double *d_state = nullptr;  // 2 parities x [2K][n_ch]
   uint32_t *d_ctrl = nullptr;
   double *d_tab = nullptr;    // coef | G | P | Q[q_cap]
@@ -180,6 +182,7 @@ struct filark_stalta_state {
   int64_t n_ch = 0;
   int64_t nsta = 0, nlta = 0;
   int waves = kDefaultWaves;
+  int block = kDefaultBlock;
   double *d_state = nullptr;  // 2 parities x [2][n_ch]
   uint32_t *d_ctrl = nullptr;
   double *d_tab = nullptr;    // aL_s, aL_l, qs[q_cap], ql[q_cap]
@@ -190,7 +193,7 @@ struct filark_stalta_state {
 namespace {
 
 filark_status sos_tables(filark_sos_state *st, int q_cap, hipStream_t stream) {
-  const int K = st->cas.K, n = 2 * K, L = kBlock;
+  const int K = st->cas.K, n = 2 * K, L = st->block;
   Mat A;
   std::vector<double> B;
   cascade_matrices(st->cas, A, B);
@@ -233,7 +236,7 @@ filark_status sos_tables(filark_sos_state *st, int q_cap, hipStream_t stream) {
 }
 
 filark_status stalta_tables(filark_stalta_state *st, int q_cap, hipStream_t stream) {
-  const int L = kBlock, S = st->waves * kBlock;
+  const int L = st->block, S = st->waves * st->block;
   const double as = 1.0 - 1.0 / (double)st->nsta, al = 1.0 - 1.0 / (double)st->nlta;
   std::vector<double> tab(2 + 2 * (size_t)q_cap);
   tab[0] = std::pow(as, L);
@@ -290,13 +293,14 @@ filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const 
   if (sos && !sl && !y) return fail(FILARK_EINVAL, "null output pointer");
   if (sl && !cf) return fail(FILARK_EINVAL, "null cf pointer");
   if (y && cf && (const void *)y == (const void *)cf) return fail(FILARK_EINVAL, "y and cf must differ");
-  if ((uint64_t)kBlock * (uint64_t)n_ch * 4u >= 0x7fffffffull)
-    return fail(FILARK_EINVAL, "row stride too large");
-
   const int waves = sos ? sos->waves : sl->waves;
-  if (sos && sl && sos->waves != sl->waves) return fail(FILARK_EINVAL, "tile shapes of the states differ");
+  const int block = sos ? sos->block : sl->block;
+  if (sos && sl && (sos->waves != sl->waves || sos->block != sl->block))
+    return fail(FILARK_EINVAL, "tile shapes of the states differ (set both with filark_tile_set)");
+  if ((uint64_t)block * (uint64_t)n_ch * 4u >= 0x7fffffffull)
+    return fail(FILARK_EINVAL, "row stride too large");
   const int K = sos ? sos->cas.K : 0;
-  const int seg_len = waves * kBlock;
+  const int seg_len = waves * block;
   const int n_seg = (int)((n_t + seg_len - 1) / seg_len);
   const int n_grp = (int)((n_ch + kWave - 1) / kWave);
   const size_t cells = (size_t)n_seg * (size_t)n_grp;
@@ -352,7 +356,7 @@ filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const 
   p.flags = ws.flags;
   p.ctrl = sos ? sos->d_ctrl : sl->d_ctrl;
   p.spin_limit = kSpinLimit;
-  hipError_t e = launch_fwd(p, K, sl != nullptr, sl == nullptr || y != nullptr, waves, stream);
+  hipError_t e = launch_fwd(p, K, block, sl != nullptr, sl == nullptr || y != nullptr, waves, stream);
   if (prev_dev != dev) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
   return FILARK_OK;
@@ -554,6 +558,46 @@ filark_status filark_state_set(void *obj, int kind, const void *host_buf, size_t
                       hipMemcpyHostToDevice));
     const uint32_t gw[2] = {(uint32_t)((uint64_t)g & 0xffffffffu), (uint32_t)((uint64_t)g >> 32)};
     HIP_TRY(hipMemcpy(st->d_ctrl + kCtrlCounter, gw, sizeof gw, hipMemcpyHostToDevice));
+    return FILARK_OK;
+  }
+  return fail(FILARK_EINVAL, "unknown state kind %d", kind);
+}
+
+filark_status filark_tile_set(void *obj, int kind, int block, int waves, hipStream_t stream) {
+  if (!obj) return fail(FILARK_EINVAL, "null state");
+  if (block != 32 && block != 64) return fail(FILARK_EINVAL, "block must be 32 or 64");
+  if (waves < 1 || waves + 1 > kMaxWaves) return fail(FILARK_EINVAL, "waves must be in [1, %d]", kMaxWaves - 1);
+  if (kind == FILARK_STATE_SOS) {
+    filark_sos_state *st = static_cast<filark_sos_state *>(obj);
+    if (st->block == block && st->waves == waves) return FILARK_OK;
+    HIP_TRY(hipStreamSynchronize(stream));
+    st->block = block;
+    st->waves = waves;
+    return sos_tables(st, std::max(16, st->q_cap), stream);
+  }
+  if (kind == FILARK_STATE_STALTA) {
+    filark_stalta_state *st = static_cast<filark_stalta_state *>(obj);
+    if (st->block == block && st->waves == waves) return FILARK_OK;
+    HIP_TRY(hipStreamSynchronize(stream));
+    st->block = block;
+    st->waves = waves;
+    return stalta_tables(st, std::max(16, st->q_cap), stream);
+  }
+  return fail(FILARK_EINVAL, "unknown state kind %d", kind);
+}
+
+filark_status filark_tile_get(const void *obj, int kind, int *block, int *waves) {
+  if (!obj || !block || !waves) return fail(FILARK_EINVAL, "null pointer");
+  if (kind == FILARK_STATE_SOS) {
+    const filark_sos_state *st = static_cast<const filark_sos_state *>(obj);
+    *block = st->block;
+    *waves = st->waves;
+    return FILARK_OK;
+  }
+  if (kind == FILARK_STATE_STALTA) {
+    const filark_stalta_state *st = static_cast<const filark_stalta_state *>(obj);
+    *block = st->block;
+    *waves = st->waves;
     return FILARK_OK;
   }
   return fail(FILARK_EINVAL, "unknown state kind %d", kind);

@@ -8,7 +8,8 @@ namespace filark {
 
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kMaxSections = 8;  // cascade length supported by the kernels
-constexpr int kBlock = 32;       // samples per lane block (L)
+constexpr int kMaxBlock = 64;    // samples per lane block L: 32 or 64
+constexpr int kMaxWaves = 9;     // data waves + 1 carry wave per workgroup
 
 // Control words of one state object (device memory, uint32 each).
 //   [0] ticket counter, [1] finished-tile counter, [2] launch epoch,
@@ -28,12 +29,12 @@ struct FwdParams {
   int32_t n_t;         // rows in this chunk
   int32_t n_seg;       // time segments per chunk (one workgroup row each)
   int32_t n_grp;       // channel groups of 64
-  int32_t seg_len;     // rows per segment = waves * kBlock
+  int32_t seg_len;     // rows per segment = waves * L
 
   // SOS cascade
   double *zs;          // state, two parity buffers of [2K][n_ch]
   const double *coef;  // [K][5] = b0, b1, b2, -a1, -a2
-  const double *G;     // [kBlock][2K]: A^(L-1-j) B, block-end state of a unit sample at j
+  const double *G;     // [L][2K]: A^(L-1-j) B, block-end state of a unit sample at j
   const double *P;     // [2K][2K]: A^L (one block)
   const double *Q;     // [n_seg][2K][2K]: (A^S)^m, m = 0 .. n_seg-1
   uint32_t *sos_ctrl;  // control words of the SOS object (epoch -> zs parity)
@@ -56,8 +57,12 @@ struct FwdParams {
   int32_t spin_limit;  // bounded wait (iterations) before flagging a timeout
 };
 
-// Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only.
-hipError_t launch_fwd(const FwdParams &p, int K, bool stalta, bool write_y, int waves,
+// Dynamic LDS bytes of a forward workgroup with `waves` data waves.
+size_t fwd_lds_bytes(int K, int waves);
+
+// Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only;
+// `waves` data waves (<= kMaxWaves - 1) plus one carry wave per workgroup.
+hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, int waves,
                       hipStream_t stream);
 
 }  // namespace filark

@@ -239,3 +239,48 @@ def test_shape_errors(F):
     st.process(torch.zeros((0, 64), device="cuda"))  # empty chunk is a no-op
     with pytest.raises(F.FilarkError):
         F.SOSState(np.array([[1.0, 0, 0, 1.0, -2.0, 1.0]]), 4)  # double pole at z = 1
+
+
+@pytest.mark.parametrize("block", [32, 64])
+@pytest.mark.parametrize("waves", [1, 2, 3, 4, 6, 8])
+def test_tile_shapes(F, block, waves):
+    """Every tile shape gives the oracle's result (ragged channels and time)."""
+    orc = _oracle()
+    g = torch.Generator(device="cuda").manual_seed(11 + block + waves)
+    n_ch, splits = 131, [1, 700, 1999, 2]
+    x = torch.randn((sum(splits), n_ch), generator=g, device="cuda", dtype=torch.float32)
+    sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
+    st = F.SOSState(sos, n_ch)
+    sl = F.StaLtaState(30 / 1500.0, 300 / 1500.0, 1500.0, n_ch)
+    st.set_tile(block, waves)
+    sl.set_tile(block, waves)
+    assert st.tile() == (block, waves) and sl.tile() == (block, waves)
+    ys, cfs, t0 = [], [], 0
+    for n in splits:
+        y, cf = F.sos_stalta_process(st, sl, x[t0:t0 + n].contiguous())
+        ys.append(y)
+        cfs.append(cf)
+        t0 += n
+    torch.cuda.synchronize()
+    st.check()
+    sl.check()
+    s = orc.Stream(sos, n_ch, 30, 300)
+    yo, cfo = s.process(x.cpu().numpy().astype(np.float64))
+    assert max_rel_rms(torch.cat(ys).cpu().numpy(), yo) <= 1e-5
+    assert max_rel_rms(torch.cat(cfs).cpu().numpy(), cfo) <= 1e-5
+    np.testing.assert_allclose(st.get_state(), s.zi, rtol=1e-6, atol=1e-6 * np.abs(s.zi).max())
+
+
+def test_tile_shape_errors(F):
+    orc = _oracle()
+    sos = orc.butter_sos(4, "bandpass", 1.0, 50.0, 500.0)
+    st = F.SOSState(sos, 64)
+    sl = F.StaLtaState(0.1, 1.0, 500.0, 64)
+    for b, w in [(16, 4), (64, 0), (64, 9), (48, 2)]:
+        with pytest.raises(F.FilarkError) as e:
+            st.set_tile(b, w)
+        assert e.value.status == F.EINVAL
+    st.set_tile(32, 2)
+    with pytest.raises(F.FilarkError) as e:  # fused call needs equal shapes
+        F.sos_stalta_process(st, sl, torch.zeros((10, 64), device="cuda"))
+    assert e.value.status == F.EINVAL
