@@ -27,8 +27,10 @@
  * Asynchrony: *_process calls only enqueue work on `stream` (a hipStream_t;
  * NULL is the null stream) and return; the caller synchronises before reading
  * outputs.  Calls that use one state object must be issued in order on one
- * stream: the state is a sequential dependency.  filark_state_get/_set and
- * filark_check synchronise `stream` themselves.
+ * stream: the state is a sequential dependency, updated in place on the
+ * device by each call.  filark_state_get/_set and filark_check synchronise
+ * `stream` themselves.  The process calls allocate nothing and may be
+ * captured in a HIP graph; each replay advances the state like a call.
  */
 #ifndef FILARK_H
 #define FILARK_H
@@ -49,7 +51,7 @@ typedef enum filark_status {
   FILARK_ENOMEM = 3,     /* host or device allocation failed */
   FILARK_EHIP = 4,       /* a HIP runtime call failed (message has details) */
   FILARK_EUNSTABLE = 5,  /* a pole on or outside the unit circle */
-  FILARK_ETIMEOUT = 6    /* a kernel's bounded wait expired (results invalid) */
+  FILARK_ETIMEOUT = 6    /* reserved (no kernel of this version waits on another) */
 } filark_status;
 
 typedef enum filark_btype {
@@ -103,7 +105,8 @@ filark_status filark_sos_init(filark_sos_t *st, const double *sos, int n_sec, in
  * (process(chunk, state) -> (output, new_state), Section 3.4).
  *   in, out  device FP32 [n_t][n_ch]; out == in is allowed (in place).
  *   n_ch     must equal the n_ch given to filark_sos_init (else FILARK_ESHAPE).
- *   n_t      samples in this chunk, 0 <= n_t <= 2^31 - 1; 0 is a no-op.
+ *   n_t      samples in this chunk, n_t >= 0; 0 is a no-op.  Chunks whose
+ *            padded byte size exceeds 2^31 run as several launches.
  * Asynchronous on `stream`.
  */
 filark_status filark_sos_process(filark_sos_t st, const float *in, float *out, int64_t n_ch,
@@ -160,19 +163,21 @@ filark_status filark_state_set(void *st, int kind, const void *host_buf, size_t 
 
 /*
  * Tile shape of a state object's kernels (a tuning knob; results do not
- * depend on it beyond FP64 rounding of the carries): `block` samples per lane
- * (32 or 64) and `waves` data waves per workgroup (1 .. 8), i.e. time
- * segments of block * waves samples.  Default 64 x 3.  Both states passed to
+ * depend on it beyond FP64 rounding of the carries).  A workgroup of `waves`
+ * waves owns `group` consecutive channels for the whole chunk and walks it in
+ * windows of waves * 64 / group blocks of `block` samples per lane.
+ *   block  32 or 64;  waves  1 .. 8;  group  4, 8, 16, 32 or 64.
+ * Default 64 x 3 x 8 (windows of 1536 rows).  Both states passed to
  * filark_sos_stalta_process must have the same shape.  _set synchronises
  * `stream` and rebuilds the scan tables; kind as for filark_state_get.
+ * FILARK_EINVAL for a shape outside the ranges above.
  */
-filark_status filark_tile_set(void *st, int kind, int block, int waves, hipStream_t stream);
-filark_status filark_tile_get(const void *st, int kind, int *block, int *waves);
+filark_status filark_tile_set(void *st, int kind, int block, int waves, int group, hipStream_t stream);
+filark_status filark_tile_get(const void *st, int kind, int *block, int *waves, int *group);
 
 /*
- * Synchronise `stream` and report whether any kernel that ran on `st`
- * (kind as above) hit its bounded-wait limit (FILARK_ETIMEOUT; the outputs of
- * that call are then invalid).  Clears the flag.
+ * Synchronise `stream` and report an asynchronous HIP error of the work
+ * enqueued on it (FILARK_EHIP).  kind as above.
  */
 filark_status filark_check(const void *st, int kind, hipStream_t stream);
 

@@ -64,8 +64,9 @@ def lib():
     L.filark_state_get.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
     L.filark_state_set.argtypes = [vp, ctypes.c_int, vp, ctypes.c_size_t, vp]
     L.filark_check.argtypes = [vp, ctypes.c_int, vp]
-    L.filark_tile_set.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
-    L.filark_tile_get.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    ip = ctypes.POINTER(ctypes.c_int)
+    L.filark_tile_set.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.filark_tile_get.argtypes = [vp, ctypes.c_int, ip, ip, ip]
     L.filark_sos_destroy.argtypes = [vp]
     L.filark_stalta_destroy.argtypes = [vp]
     for name in EXPORTS:
@@ -152,13 +153,15 @@ class SOSState:
     def check(self, stream=None):
         _check(lib().filark_check(self._h, STATE_SOS, _stream(stream)))
 
-    def set_tile(self, block: int, waves: int, stream=None):
-        _check(lib().filark_tile_set(self._h, STATE_SOS, int(block), int(waves), _stream(stream)))
+    def set_tile(self, block: int, waves: int, group: int = 8, stream=None):
+        """Tile shape: `block` samples per lane, `waves` per workgroup, `group`
+        channels per workgroup."""
+        _check(lib().filark_tile_set(self._h, STATE_SOS, int(block), int(waves), int(group), _stream(stream)))
 
     def tile(self):
-        b, w = ctypes.c_int(), ctypes.c_int()
-        _check(lib().filark_tile_get(self._h, STATE_SOS, ctypes.byref(b), ctypes.byref(w)))
-        return b.value, w.value
+        b, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().filark_tile_get(self._h, STATE_SOS, ctypes.byref(b), ctypes.byref(w), ctypes.byref(g)))
+        return b.value, w.value, g.value
 
     def close(self):
         if self._h:
@@ -211,13 +214,15 @@ class StaLtaState:
     def check(self, stream=None):
         _check(lib().filark_check(self._h, STATE_STALTA, _stream(stream)))
 
-    def set_tile(self, block: int, waves: int, stream=None):
-        _check(lib().filark_tile_set(self._h, STATE_STALTA, int(block), int(waves), _stream(stream)))
+    def set_tile(self, block: int, waves: int, group: int = 8, stream=None):
+        """Tile shape: `block` samples per lane, `waves` per workgroup, `group`
+        channels per workgroup."""
+        _check(lib().filark_tile_set(self._h, STATE_STALTA, int(block), int(waves), int(group), _stream(stream)))
 
     def tile(self):
-        b, w = ctypes.c_int(), ctypes.c_int()
-        _check(lib().filark_tile_get(self._h, STATE_STALTA, ctypes.byref(b), ctypes.byref(w)))
-        return b.value, w.value
+        b, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().filark_tile_get(self._h, STATE_STALTA, ctypes.byref(b), ctypes.byref(w), ctypes.byref(g)))
+        return b.value, w.value, g.value
 
     def close(self):
         if self._h:

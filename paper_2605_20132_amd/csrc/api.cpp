@@ -3,12 +3,10 @@
 //
 // Every operator follows process(chunk, state) -> (output, new_state)
 // (FiLark Section 3.4): the device state a call leaves behind is where the
-// next call starts.  Device state buffers are double-buffered by launch
-// parity: a launch reads parity e & 1 and its last block writes parity
-// (e & 1) ^ 1, where e is the object's launch epoch that the last finishing
-// workgroup advances on the device.  Hence a chunk's initial state is never
-// overwritten while tiles of the same launch may still read it, and repeated
-// launches (including graph replays) need no host bookkeeping.
+// next call starts.  A workgroup owns its channels for the whole chunk, so it
+// reads their state at its start and overwrites it at its end, in place; no
+// other workgroup touches them, and repeated launches (including graph
+// replays) need no host bookkeeping.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,7 +24,6 @@
 namespace filark {
 filark_status design_butterworth(int order, int btype, double f1, double f2, double fs,
                                  double *sos_out, int *n_sec, const char **why);
-size_t fwd_lds_bytes(int K, int waves);
 }  // namespace filark
 
 using namespace filark;
@@ -51,9 +48,27 @@ filark_status fail(filark_status st, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(FILARK_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int kDefaultWaves = 3;
+// Default tile: 64-sample blocks, 3 waves, groups of 8 channels, i.e. one
+// workgroup covers 1536 rows of 8 channels per window.
 constexpr int kDefaultBlock = 64;
-constexpr int kSpinLimit = 1 << 22;
+constexpr int kDefaultWaves = 3;
+constexpr int kDefaultGroup = 8;
+
+struct Tile {
+  int block = kDefaultBlock;  // L: samples per lane block
+  int waves = kDefaultWaves;  // waves per workgroup
+  int group = kDefaultGroup;  // channels per workgroup
+  bool operator==(const Tile &o) const {
+    return block == o.block && waves == o.waves && group == o.group;
+  }
+  int blocks() const { return waves * kWave / group; }  // NB: blocks per window
+  int window() const { return blocks() * block; }       // rows per window
+  int levels() const {
+    int k = 0;
+    while ((1 << k) < blocks()) ++k;
+    return std::max(1, k);
+  }
+};
 
 // Dense row-major n x n matrices in FP64.
 using Mat = std::vector<double>;
@@ -125,36 +140,6 @@ bool section_stable(double a1, double a2) {
   return std::abs(r1) < 1.0 && std::abs(r2) < 1.0;
 }
 
-struct Workspace {
-  double *rec = nullptr;
-  uint32_t *flags = nullptr;
-  size_t cells = 0;
-  int ns = 0;
-};
-
-void ws_free(Workspace &w) {
-  if (w.rec) (void)hipFree(w.rec);
-  if (w.flags) (void)hipFree(w.flags);
-  w = Workspace();
-}
-
-// Grow the look-back workspace to hold `cells` tiles with NS-wide SOS records.
-filark_status ws_ensure(Workspace &w, size_t cells, int ns, hipStream_t stream) {
-  if (w.rec && cells <= w.cells && ns <= w.ns) return FILARK_OK;
-  const size_t c2 = std::max(cells, w.cells);
-  const int n2 = std::max(ns, w.ns);
-  HIP_TRY(hipStreamSynchronize(stream));
-  ws_free(w);
-  const size_t rec_doubles = c2 * (size_t)(2 * n2 * kWave + 2 * 2 * kWave);
-  HIP_TRY(hipMalloc(&w.rec, rec_doubles * sizeof(double)));
-  HIP_TRY(hipMalloc(&w.flags, 2 * c2 * sizeof(uint32_t)));
-  HIP_TRY(hipMemsetAsync(w.flags, 0, 2 * c2 * sizeof(uint32_t), stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  w.cells = c2;
-  w.ns = n2;
-  return FILARK_OK;
-}
-
 int current_device() {
   int d = 0;
   (void)hipGetDevice(&d);
@@ -167,33 +152,39 @@ struct filark_sos_state {
   int device = 0;
   int64_t n_ch = 0;
   Cascade cas;
-  int waves = kDefaultWaves;
-  int block = kDefaultBlock;
-  double *d_state = nullptr;  // 2 parities x [2K][n_ch]
-  uint32_t *d_ctrl = nullptr;
-  double *d_tab = nullptr;    // coef | G | P | Q[q_cap]
-  int q_cap = 0;
-  size_t off_G = 0, off_P = 0, off_Q = 0;
-  Workspace ws;
+  Tile tile;
+  double *d_state = nullptr;  // [2K][n_ch]
+  double *d_tab = nullptr;    // coef | G | Pw
+  size_t off_G = 0, off_P = 0;
 };
 
 struct filark_stalta_state {
   int device = 0;
   int64_t n_ch = 0;
   int64_t nsta = 0, nlta = 0;
-  int waves = kDefaultWaves;
-  int block = kDefaultBlock;
-  double *d_state = nullptr;  // 2 parities x [2][n_ch]
-  uint32_t *d_ctrl = nullptr;
-  double *d_tab = nullptr;    // aL_s, aL_l, qs[q_cap], ql[q_cap]
-  int q_cap = 0;
-  Workspace ws;
+  Tile tile;
+  double *d_state = nullptr;  // [2][n_ch] (sta, lta)
+  int64_t *d_cnt = nullptr;   // [n_ch] global sample counter
+  double *d_tab = nullptr;    // decay powers
 };
 
 namespace {
 
-filark_status sos_tables(filark_sos_state *st, int q_cap, hipStream_t stream) {
-  const int K = st->cas.K, n = 2 * K, L = st->block;
+filark_status upload(double **dst, const std::vector<double> &tab, hipStream_t stream) {
+  if (*dst) {
+    HIP_TRY(hipStreamSynchronize(stream));
+    (void)hipFree(*dst);
+    *dst = nullptr;
+  }
+  HIP_TRY(hipMalloc(dst, tab.size() * sizeof(double)));
+  HIP_TRY(hipMemcpyAsync(*dst, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  return FILARK_OK;
+}
+
+// coef [K][5] = b0 b1 b2 -a1 -a2 | G [L][2K] = A^(L-1-j) B | Pw [levels][2K][2K] = A^(L 2^k)
+filark_status sos_tables(filark_sos_state *st, hipStream_t stream) {
+  const int K = st->cas.K, n = 2 * K, L = st->tile.block;
   Mat A;
   std::vector<double> B;
   cascade_matrices(st->cas, A, B);
@@ -212,76 +203,35 @@ filark_status sos_tables(filark_sos_state *st, int q_cap, hipStream_t stream) {
   st->off_P = tab.size();
   Mat P = identity(n);
   for (int j = 0; j < L; ++j) P = matmul(A, P, n);
-  tab.insert(tab.end(), P.begin(), P.end());
-  while (tab.size() % 8) tab.push_back(0.0);
-  st->off_Q = tab.size();
-  Mat Qs = identity(n);
-  for (int w = 0; w < st->waves; ++w) Qs = matmul(P, Qs, n);
-  Mat Qm = identity(n);
-  for (int m = 0; m < q_cap; ++m) {
-    tab.insert(tab.end(), Qm.begin(), Qm.end());
-    Qm = matmul(Qs, Qm, n);
+  for (int k = 0; k < st->tile.levels(); ++k) {
+    tab.insert(tab.end(), P.begin(), P.end());
+    P = matmul(P, P, n);
   }
-  if (st->d_tab) {
-    HIP_TRY(hipStreamSynchronize(stream));
-    (void)hipFree(st->d_tab);
-    st->d_tab = nullptr;
-  }
-  HIP_TRY(hipMalloc(&st->d_tab, tab.size() * sizeof(double)));
-  HIP_TRY(hipMemcpyAsync(st->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
-                         stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  st->q_cap = q_cap;
-  return FILARK_OK;
+  return upload(&st->d_tab, tab, stream);
 }
 
-filark_status stalta_tables(filark_stalta_state *st, int q_cap, hipStream_t stream) {
-  const int L = st->block, S = st->waves * st->block;
+// [levels][2] = (as, al)^(L 2^k), then [L + 1][2] = (as, al)^m, as = 1 - 1/nsta, al = 1 - 1/nlta
+filark_status stalta_tables(filark_stalta_state *st, hipStream_t stream) {
+  const int L = st->tile.block;
   const double as = 1.0 - 1.0 / (double)st->nsta, al = 1.0 - 1.0 / (double)st->nlta;
-  std::vector<double> tab(2 + 2 * (size_t)q_cap);
-  tab[0] = std::pow(as, L);
-  tab[1] = std::pow(al, L);
-  for (int m = 0; m < q_cap; ++m) {
-    tab[2 + m] = std::pow(as, (double)S * m);
-    tab[2 + q_cap + m] = std::pow(al, (double)S * m);
+  std::vector<double> tab;
+  for (int k = 0; k < st->tile.levels(); ++k) {
+    const double e = (double)L * std::ldexp(1.0, k);
+    tab.push_back(std::pow(as, e));
+    tab.push_back(std::pow(al, e));
   }
-  if (st->d_tab) {
-    HIP_TRY(hipStreamSynchronize(stream));
-    (void)hipFree(st->d_tab);
-    st->d_tab = nullptr;
+  for (int m = 0; m <= L; ++m) {
+    tab.push_back(std::pow(as, (double)m));
+    tab.push_back(std::pow(al, (double)m));
   }
-  HIP_TRY(hipMalloc(&st->d_tab, tab.size() * sizeof(double)));
-  HIP_TRY(hipMemcpyAsync(st->d_tab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
-                         stream));
-  HIP_TRY(hipStreamSynchronize(stream));
-  st->q_cap = q_cap;
-  return FILARK_OK;
-}
-
-int round_cap(int need) {
-  int c = 16;
-  while (c < need) c *= 2;
-  return c;
-}
-
-filark_status alloc_ctrl(uint32_t **ctrl, hipStream_t stream) {
-  HIP_TRY(hipMalloc(ctrl, kCtrlWords * sizeof(uint32_t)));
-  HIP_TRY(hipMemsetAsync(*ctrl, 0, kCtrlWords * sizeof(uint32_t), stream));
-  return FILARK_OK;
-}
-
-filark_status read_ctrl(const uint32_t *d_ctrl, uint32_t *h, hipStream_t stream) {
-  HIP_TRY(hipStreamSynchronize(stream));
-  HIP_TRY(hipMemcpy(h, d_ctrl, kCtrlWords * sizeof(uint32_t), hipMemcpyDeviceToHost));
-  return FILARK_OK;
+  return upload(&st->d_tab, tab, stream);
 }
 
 // Shared launch path of the three processing entry points.
 filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const float *in,
                           float *y, float *cf, int64_t n_ch, int64_t n_t, hipStream_t stream) {
-  if (n_t < 0 || n_t > 0x7fffffff) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
+  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
   if (n_ch < 1) return fail(FILARK_EINVAL, "n_ch must be >= 1");
-  if (n_ch > (int64_t)1 << 24) return fail(FILARK_EINVAL, "n_ch above 2^24 is not supported");
   if (sos && sos->n_ch != n_ch)
     return fail(FILARK_ESHAPE, "n_ch %lld differs from the SOS state's %lld", (long long)n_ch,
                 (long long)sos->n_ch);
@@ -293,56 +243,50 @@ filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const 
   if (sos && !sl && !y) return fail(FILARK_EINVAL, "null output pointer");
   if (sl && !cf) return fail(FILARK_EINVAL, "null cf pointer");
   if (y && cf && (const void *)y == (const void *)cf) return fail(FILARK_EINVAL, "y and cf must differ");
-  const int waves = sos ? sos->waves : sl->waves;
-  const int block = sos ? sos->block : sl->block;
-  if (sos && sl && (sos->waves != sl->waves || sos->block != sl->block))
+  const Tile t = sos ? sos->tile : sl->tile;
+  if (sos && sl && !(sos->tile == sl->tile))
     return fail(FILARK_EINVAL, "tile shapes of the states differ (set both with filark_tile_set)");
-  if ((uint64_t)block * (uint64_t)n_ch * 4u >= 0x7fffffffull)
-    return fail(FILARK_EINVAL, "row stride too large");
+  // A launch covers one window of rows; longer chunks run as consecutive
+  // launches on the stream, the state carrying through device memory.  Byte
+  // offsets within a launch are 32-bit: the window's padded extent must stay
+  // below 2^31 bytes.
+  const uint64_t rowb = (uint64_t)n_ch * 4u;
+  const int64_t rows = t.window();
+  if ((uint64_t)rows * rowb > 0x7fffffffull)
+    return fail(FILARK_EINVAL, "n_ch %lld too large for a %d-row window (at most %lld channels)",
+                (long long)n_ch, (int)rows, (long long)(0x7fffffffull / (uint64_t)rows / 4u));
   const int K = sos ? sos->cas.K : 0;
-  const int seg_len = waves * block;
-  const int n_seg = (int)((n_t + seg_len - 1) / seg_len);
-  const int n_grp = (int)((n_ch + kWave - 1) / kWave);
-  const size_t cells = (size_t)n_seg * (size_t)n_grp;
-  if (cells > 0x7fffffffull) return fail(FILARK_EINVAL, "too many tiles");
 
   int prev_dev = current_device();
   const int dev = sos ? sos->device : sl->device;
+  int lds_max = 0;
+  HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  const size_t lds = fwd_lds_bytes(K, t.waves, t.levels());
+  if (lds > (size_t)lds_max)
+    return fail(FILARK_EINVAL, "tile %dx%dx%d needs %zu bytes of LDS for %d sections (device limit %d)",
+                t.block, t.waves, t.group, lds, K, lds_max);
   if (prev_dev != dev) HIP_TRY(hipSetDevice(dev));
-
-  filark_status rc = FILARK_OK;
-  if (sos && n_seg > sos->q_cap) rc = sos_tables(sos, round_cap(n_seg), stream);
-  if (rc == FILARK_OK && sl && n_seg > sl->q_cap) rc = stalta_tables(sl, round_cap(n_seg), stream);
-  Workspace &ws = sos ? sos->ws : sl->ws;
-  if (rc == FILARK_OK) rc = ws_ensure(ws, cells, 2 * K, stream);
-  if (rc != FILARK_OK) {
-    if (prev_dev != dev) (void)hipSetDevice(prev_dev);
-    return rc;
-  }
 
   FwdParams p;
   std::memset(&p, 0, sizeof p);
-  p.x = in;
-  p.y = y;
-  p.cf = cf;
   p.n_ch = n_ch;
-  p.n_t = (int32_t)n_t;
-  p.n_seg = n_seg;
-  p.n_grp = n_grp;
-  p.seg_len = seg_len;
+  int cwl = 0;
+  while ((1 << cwl) < t.group) ++cwl;
+  p.cw_log2 = cwl;
+  p.nw = t.waves;
+  p.n_grp = (int)((n_ch + t.group - 1) / t.group);
+  p.xq = std::max(1, 32 / t.group);  // groups sharing one 128-byte line
+  p.n_lev = t.levels();
   if (sos) {
     p.zs = sos->d_state;
     p.coef = sos->d_tab;
     p.G = sos->d_tab + sos->off_G;
-    p.P = sos->d_tab + sos->off_P;
-    p.Q = sos->d_tab + sos->off_Q;
-    p.sos_ctrl = sos->d_ctrl;
+    p.Pw = sos->d_tab + sos->off_P;
   }
   if (sl) {
     p.sl = sl->d_state;
-    p.slq = sl->d_tab;
-    p.q_cap = sl->q_cap;
-    p.sl_ctrl = sl->d_ctrl;
+    p.cnt = sl->d_cnt;
+    p.dpow = sl->d_tab;
     p.nlta = sl->nlta;
     p.nsta_d = (double)sl->nsta;
     p.nlta_d = (double)sl->nlta;
@@ -352,13 +296,27 @@ filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const 
     p.al = (float)p.ald;
     p.kappa = (float)((double)sl->nlta / (double)sl->nsta);
   }
-  p.rec = ws.rec;
-  p.flags = ws.flags;
-  p.ctrl = sos ? sos->d_ctrl : sl->d_ctrl;
-  p.spin_limit = kSpinLimit;
-  hipError_t e = launch_fwd(p, K, block, sl != nullptr, sl == nullptr || y != nullptr, waves, stream);
+  hipError_t e = hipSuccess;
+  for (int64_t t0 = 0; t0 < n_t && e == hipSuccess; t0 += rows) {
+    const int64_t nt = std::min(rows, n_t - t0);
+    const size_t off = (size_t)t0 * (size_t)n_ch;
+    p.x = in + off;
+    p.y = y ? y + off : nullptr;
+    p.cf = cf ? cf + off : nullptr;
+    p.n_t = (int32_t)nt;
+    p.range = (int32_t)((uint64_t)nt * rowb);
+    e = launch_fwd(p, K, t.block, sl != nullptr, sl == nullptr || y != nullptr, stream);
+  }
   if (prev_dev != dev) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status check_tile(int block, int waves, int group) {
+  if (block != 32 && block != 64) return fail(FILARK_EINVAL, "block must be 32 or 64");
+  if (waves < 1 || waves > kMaxWaves) return fail(FILARK_EINVAL, "waves must be in [1, %d]", kMaxWaves);
+  if (group != 4 && group != 8 && group != 16 && group != 32 && group != 64)
+    return fail(FILARK_EINVAL, "group must be 4, 8, 16, 32 or 64 channels");
   return FILARK_OK;
 }
 
@@ -368,7 +326,7 @@ extern "C" {
 
 const char *filark_last_error(void) { return g_err.c_str(); }
 
-const char *filark_version(void) { return "filark-mi355x 0.1 (gfx950)"; }
+const char *filark_version(void) { return "filark-mi355x 0.2 (gfx950)"; }
 
 filark_status filark_sos_design(int order, int btype, double f1, double f2, double fs,
                                 double *sos_out, int *n_sec) {
@@ -406,13 +364,12 @@ filark_status filark_sos_init(filark_sos_t *out, const double *sos, int n_sec, i
   st->device = current_device();
   st->n_ch = n_ch;
   st->cas = cas;
-  const size_t bytes = 2 * (size_t)(2 * n_sec) * (size_t)n_ch * sizeof(double);
+  const size_t bytes = (size_t)(2 * n_sec) * (size_t)n_ch * sizeof(double);
   filark_status rc = FILARK_OK;
   hipError_t e = hipMalloc(&st->d_state, bytes);
   if (e == hipSuccess) e = hipMemsetAsync(st->d_state, 0, bytes, stream);
   if (e != hipSuccess) rc = fail(FILARK_EHIP, "state allocation: %s", hipGetErrorString(e));
-  if (rc == FILARK_OK) rc = alloc_ctrl(&st->d_ctrl, stream);
-  if (rc == FILARK_OK) rc = sos_tables(st, 16, stream);
+  if (rc == FILARK_OK) rc = sos_tables(st, stream);
   if (rc != FILARK_OK) {
     filark_sos_destroy(st);
     return rc;
@@ -437,13 +394,14 @@ filark_status filark_stalta_init(filark_stalta_t *out, double sta_s, double lta_
   st->n_ch = n_ch;
   st->nsta = (int64_t)ns;
   st->nlta = (int64_t)nl;
-  const size_t bytes = 2 * 2 * (size_t)n_ch * sizeof(double);
+  const size_t bytes = 2 * (size_t)n_ch * sizeof(double);
   filark_status rc = FILARK_OK;
   hipError_t e = hipMalloc(&st->d_state, bytes);
   if (e == hipSuccess) e = hipMemsetAsync(st->d_state, 0, bytes, stream);
+  if (e == hipSuccess) e = hipMalloc(&st->d_cnt, (size_t)n_ch * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemsetAsync(st->d_cnt, 0, (size_t)n_ch * sizeof(int64_t), stream);
   if (e != hipSuccess) rc = fail(FILARK_EHIP, "state allocation: %s", hipGetErrorString(e));
-  if (rc == FILARK_OK) rc = alloc_ctrl(&st->d_ctrl, stream);
-  if (rc == FILARK_OK) rc = stalta_tables(st, 16, stream);
+  if (rc == FILARK_OK) rc = stalta_tables(st, stream);
   if (rc != FILARK_OK) {
     filark_stalta_destroy(st);
     return rc;
@@ -475,18 +433,14 @@ filark_status filark_sos_stalta_process(filark_sos_t sos, filark_stalta_t sl, co
 filark_status filark_state_get(const void *obj, int kind, void *host_buf, size_t bytes,
                                hipStream_t stream) {
   if (!obj || !host_buf) return fail(FILARK_EINVAL, "null pointer");
-  uint32_t ctrl[kCtrlWords];
   if (kind == FILARK_STATE_SOS) {
     const filark_sos_state *st = static_cast<const filark_sos_state *>(obj);
     const int n = 2 * st->cas.K;
     const size_t need = (size_t)st->n_ch * n * sizeof(double);
     if (bytes != need) return fail(FILARK_EINVAL, "state_get: need %zu bytes, got %zu", need, bytes);
-    filark_status rc = read_ctrl(st->d_ctrl, ctrl, stream);
-    if (rc) return rc;
-    const int par = (int)(ctrl[kCtrlEpoch] & 1u);
+    HIP_TRY(hipStreamSynchronize(stream));
     std::vector<double> tmp((size_t)n * st->n_ch);
-    HIP_TRY(hipMemcpy(tmp.data(), st->d_state + (size_t)par * n * st->n_ch, tmp.size() * sizeof(double),
-                      hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(tmp.data(), st->d_state, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
     double *o = static_cast<double *>(host_buf);
     for (int64_t c = 0; c < st->n_ch; ++c)
       for (int i = 0; i < n; ++i) o[c * n + i] = tmp[(size_t)i * st->n_ch + c];
@@ -496,18 +450,16 @@ filark_status filark_state_get(const void *obj, int kind, void *host_buf, size_t
     const filark_stalta_state *st = static_cast<const filark_stalta_state *>(obj);
     const size_t need = (size_t)st->n_ch * 2 * sizeof(double) + sizeof(int64_t);
     if (bytes != need) return fail(FILARK_EINVAL, "state_get: need %zu bytes, got %zu", need, bytes);
-    filark_status rc = read_ctrl(st->d_ctrl, ctrl, stream);
-    if (rc) return rc;
-    const int par = (int)(ctrl[kCtrlEpoch] & 1u);
+    HIP_TRY(hipStreamSynchronize(stream));
     std::vector<double> tmp(2 * (size_t)st->n_ch);
-    HIP_TRY(hipMemcpy(tmp.data(), st->d_state + (size_t)par * 2 * st->n_ch, tmp.size() * sizeof(double),
-                      hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(tmp.data(), st->d_state, tmp.size() * sizeof(double), hipMemcpyDeviceToHost));
+    int64_t g = 0;
+    HIP_TRY(hipMemcpy(&g, st->d_cnt, sizeof g, hipMemcpyDeviceToHost));
     double *o = static_cast<double *>(host_buf);
     for (int64_t c = 0; c < st->n_ch; ++c) {
       o[2 * c] = tmp[c];
       o[2 * c + 1] = tmp[st->n_ch + c];
     }
-    const int64_t g = (int64_t)(((uint64_t)ctrl[kCtrlCounter + 1] << 32) | ctrl[kCtrlCounter]);
     std::memcpy(o + 2 * st->n_ch, &g, sizeof g);
     return FILARK_OK;
   }
@@ -517,7 +469,6 @@ filark_status filark_state_get(const void *obj, int kind, void *host_buf, size_t
 filark_status filark_state_set(void *obj, int kind, const void *host_buf, size_t bytes,
                                hipStream_t stream) {
   if (!obj || !host_buf) return fail(FILARK_EINVAL, "null pointer");
-  uint32_t ctrl[kCtrlWords];
   if (kind == FILARK_STATE_SOS) {
     filark_sos_state *st = static_cast<filark_sos_state *>(obj);
     const int n = 2 * st->cas.K;
@@ -526,14 +477,11 @@ filark_status filark_state_set(void *obj, int kind, const void *host_buf, size_t
     const double *src = static_cast<const double *>(host_buf);
     for (size_t i = 0; i < (size_t)st->n_ch * n; ++i)
       if (!std::isfinite(src[i])) return fail(FILARK_EINVAL, "state_set: non-finite value");
-    filark_status rc = read_ctrl(st->d_ctrl, ctrl, stream);
-    if (rc) return rc;
-    const int par = (int)(ctrl[kCtrlEpoch] & 1u);
     std::vector<double> tmp((size_t)n * st->n_ch);
     for (int64_t c = 0; c < st->n_ch; ++c)
       for (int i = 0; i < n; ++i) tmp[(size_t)i * st->n_ch + c] = src[c * n + i];
-    HIP_TRY(hipMemcpy(st->d_state + (size_t)par * n * st->n_ch, tmp.data(), tmp.size() * sizeof(double),
-                      hipMemcpyHostToDevice));
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMemcpy(st->d_state, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
     return FILARK_OK;
   }
   if (kind == FILARK_STATE_STALTA) {
@@ -546,86 +494,70 @@ filark_status filark_state_set(void *obj, int kind, const void *host_buf, size_t
     int64_t g;
     std::memcpy(&g, src + 2 * st->n_ch, sizeof g);
     if (g < 0) return fail(FILARK_EINVAL, "state_set: negative sample counter");
-    filark_status rc = read_ctrl(st->d_ctrl, ctrl, stream);
-    if (rc) return rc;
-    const int par = (int)(ctrl[kCtrlEpoch] & 1u);
     std::vector<double> tmp(2 * (size_t)st->n_ch);
     for (int64_t c = 0; c < st->n_ch; ++c) {
       tmp[c] = src[2 * c];
       tmp[st->n_ch + c] = src[2 * c + 1];
     }
-    HIP_TRY(hipMemcpy(st->d_state + (size_t)par * 2 * st->n_ch, tmp.data(), tmp.size() * sizeof(double),
-                      hipMemcpyHostToDevice));
-    const uint32_t gw[2] = {(uint32_t)((uint64_t)g & 0xffffffffu), (uint32_t)((uint64_t)g >> 32)};
-    HIP_TRY(hipMemcpy(st->d_ctrl + kCtrlCounter, gw, sizeof gw, hipMemcpyHostToDevice));
+    const std::vector<int64_t> gv((size_t)st->n_ch, g);
+    HIP_TRY(hipStreamSynchronize(stream));
+    HIP_TRY(hipMemcpy(st->d_state, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(st->d_cnt, gv.data(), gv.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     return FILARK_OK;
   }
   return fail(FILARK_EINVAL, "unknown state kind %d", kind);
 }
 
-filark_status filark_tile_set(void *obj, int kind, int block, int waves, hipStream_t stream) {
+filark_status filark_tile_set(void *obj, int kind, int block, int waves, int group, hipStream_t stream) {
   if (!obj) return fail(FILARK_EINVAL, "null state");
-  if (block != 32 && block != 64) return fail(FILARK_EINVAL, "block must be 32 or 64");
-  if (waves < 1 || waves + 1 > kMaxWaves) return fail(FILARK_EINVAL, "waves must be in [1, %d]", kMaxWaves - 1);
+  filark_status rc = check_tile(block, waves, group);
+  if (rc != FILARK_OK) return rc;
+  Tile t;
+  t.block = block;
+  t.waves = waves;
+  t.group = group;
   if (kind == FILARK_STATE_SOS) {
     filark_sos_state *st = static_cast<filark_sos_state *>(obj);
-    if (st->block == block && st->waves == waves) return FILARK_OK;
+    if (st->tile == t) return FILARK_OK;
     HIP_TRY(hipStreamSynchronize(stream));
-    st->block = block;
-    st->waves = waves;
-    return sos_tables(st, std::max(16, st->q_cap), stream);
+    st->tile = t;
+    return sos_tables(st, stream);
   }
   if (kind == FILARK_STATE_STALTA) {
     filark_stalta_state *st = static_cast<filark_stalta_state *>(obj);
-    if (st->block == block && st->waves == waves) return FILARK_OK;
+    if (st->tile == t) return FILARK_OK;
     HIP_TRY(hipStreamSynchronize(stream));
-    st->block = block;
-    st->waves = waves;
-    return stalta_tables(st, std::max(16, st->q_cap), stream);
+    st->tile = t;
+    return stalta_tables(st, stream);
   }
   return fail(FILARK_EINVAL, "unknown state kind %d", kind);
 }
 
-filark_status filark_tile_get(const void *obj, int kind, int *block, int *waves) {
-  if (!obj || !block || !waves) return fail(FILARK_EINVAL, "null pointer");
-  if (kind == FILARK_STATE_SOS) {
-    const filark_sos_state *st = static_cast<const filark_sos_state *>(obj);
-    *block = st->block;
-    *waves = st->waves;
-    return FILARK_OK;
-  }
-  if (kind == FILARK_STATE_STALTA) {
-    const filark_stalta_state *st = static_cast<const filark_stalta_state *>(obj);
-    *block = st->block;
-    *waves = st->waves;
-    return FILARK_OK;
-  }
-  return fail(FILARK_EINVAL, "unknown state kind %d", kind);
+filark_status filark_tile_get(const void *obj, int kind, int *block, int *waves, int *group) {
+  if (!obj || !block || !waves || !group) return fail(FILARK_EINVAL, "null pointer");
+  Tile t;
+  if (kind == FILARK_STATE_SOS) t = static_cast<const filark_sos_state *>(obj)->tile;
+  else if (kind == FILARK_STATE_STALTA) t = static_cast<const filark_stalta_state *>(obj)->tile;
+  else return fail(FILARK_EINVAL, "unknown state kind %d", kind);
+  *block = t.block;
+  *waves = t.waves;
+  *group = t.group;
+  return FILARK_OK;
 }
 
 filark_status filark_check(const void *obj, int kind, hipStream_t stream) {
   if (!obj) return fail(FILARK_EINVAL, "null state");
-  uint32_t *d_ctrl;
-  if (kind == FILARK_STATE_SOS) d_ctrl = static_cast<const filark_sos_state *>(obj)->d_ctrl;
-  else if (kind == FILARK_STATE_STALTA) d_ctrl = static_cast<const filark_stalta_state *>(obj)->d_ctrl;
-  else return fail(FILARK_EINVAL, "unknown state kind %d", kind);
-  uint32_t ctrl[kCtrlWords];
-  filark_status rc = read_ctrl(d_ctrl, ctrl, stream);
-  if (rc) return rc;
-  if (ctrl[kCtrlError]) {
-    const uint32_t zero = 0;
-    HIP_TRY(hipMemcpy(d_ctrl + kCtrlError, &zero, sizeof zero, hipMemcpyHostToDevice));
-    return fail(FILARK_ETIMEOUT, "a look-back wait exceeded its bound (error bits 0x%x)", ctrl[kCtrlError]);
-  }
+  if (kind != FILARK_STATE_SOS && kind != FILARK_STATE_STALTA)
+    return fail(FILARK_EINVAL, "unknown state kind %d", kind);
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipGetLastError());
   return FILARK_OK;
 }
 
 filark_status filark_sos_destroy(filark_sos_t st) {
   if (!st) return FILARK_OK;
   if (st->d_state) (void)hipFree(st->d_state);
-  if (st->d_ctrl) (void)hipFree(st->d_ctrl);
   if (st->d_tab) (void)hipFree(st->d_tab);
-  ws_free(st->ws);
   delete st;
   return FILARK_OK;
 }
@@ -633,9 +565,8 @@ filark_status filark_sos_destroy(filark_sos_t st) {
 filark_status filark_stalta_destroy(filark_stalta_t st) {
   if (!st) return FILARK_OK;
   if (st->d_state) (void)hipFree(st->d_state);
-  if (st->d_ctrl) (void)hipFree(st->d_ctrl);
+  if (st->d_cnt) (void)hipFree(st->d_cnt);
   if (st->d_tab) (void)hipFree(st->d_tab);
-  ws_free(st->ws);
   delete st;
   return FILARK_OK;
 }

@@ -8,61 +8,55 @@ namespace filark {
 
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kMaxSections = 8;  // cascade length supported by the kernels
-constexpr int kMaxBlock = 64;    // samples per lane block L: 32 or 64
-constexpr int kMaxWaves = 9;     // data waves + 1 carry wave per workgroup
-
-// Control words of one state object (device memory, uint32 each).
-//   [0] ticket counter, [1] finished-tile counter, [2] launch epoch,
-//   [3] error bits, [4..5] int64 global sample counter (STA/LTA objects).
-enum { kCtrlTicket = 0, kCtrlDone = 1, kCtrlEpoch = 2, kCtrlError = 3, kCtrlCounter = 4, kCtrlWords = 8 };
-enum { kErrTimeout = 1 };
-
-// Look-back flag encoding: (epoch << 2) | status.
-enum { kFlagAggregate = 1, kFlagInclusive = 2 };
+constexpr int kMaxWaves = 8;     // waves per workgroup
+constexpr int kMaxLevels = 9;    // scan levels: blocks per window <= 2^9
 
 // Parameters of the fused forward kernel (SOS cascade and/or STA/LTA).
+//
+// Work split: channel group g (cw = 2^cw_log2 consecutive channels) belongs to
+// one workgroup, which covers a window of up to NB = nw * 64 / cw blocks of L
+// rows.  Lane (r, cl) of wave w holds channel g*cw + cl and block
+// b = w * (64 / cw) + r.  Longer chunks are launched window by window.
 struct FwdParams {
   const float *x;      // input  [n_t][n_ch]
   float *y;            // filter output [n_t][n_ch] or nullptr
   float *cf;           // characteristic function [n_t][n_ch] or nullptr
   int64_t n_ch;        // channels = row stride
-  int32_t n_t;         // rows in this chunk
-  int32_t n_seg;       // time segments per chunk (one workgroup row each)
-  int32_t n_grp;       // channel groups of 64
-  int32_t seg_len;     // rows per segment = waves * L
+  int32_t n_t;         // rows in this launch (1 .. NB * L)
+  int32_t cw_log2;     // log2 of channels per group
+  int32_t nw;          // waves per workgroup
+  int32_t n_grp;       // channel groups
+  int32_t xq;          // consecutive groups placed on one XCD
+  int32_t n_lev;       // scan levels (>= 1; level k spans 2^k blocks)
+  int32_t range;       // bytes of one [n_t][n_ch] FP32 array (buffer range)
 
   // SOS cascade
-  double *zs;          // state, two parity buffers of [2K][n_ch]
+  double *zs;          // carried state [2K][n_ch], updated in place
   const double *coef;  // [K][5] = b0, b1, b2, -a1, -a2
-  const double *G;     // [L][2K]: A^(L-1-j) B, block-end state of a unit sample at j
-  const double *P;     // [2K][2K]: A^L (one block)
-  const double *Q;     // [n_seg][2K][2K]: (A^S)^m, m = 0 .. n_seg-1
-  uint32_t *sos_ctrl;  // control words of the SOS object (epoch -> zs parity)
+  const double *G;     // [L][2K]: A^(L-1-j) B, block-end state of a unit sample at row j
+  const double *Pw;    // [n_lev][2K][2K]: A^(L 2^k)
 
   // STA/LTA
-  double *sl;          // state, two parity buffers of [2][n_ch] = (sta, lta)
+  double *sl;          // carried state [2][n_ch] = (sta, lta), updated in place
+  int64_t *cnt;        // [n_ch] global sample counter (equal for all channels)
+  const double *dpow;  // [n_lev][2] decays^(L 2^k), then [L + 1][2] decays^m
   double asd, ald;     // FP64 decay factors 1 - 1/nsta, 1 - 1/nlta
-  const double *slq;   // [2 + 2 q_cap]: alpha_s^L, alpha_l^L, alpha_s^(S m) (m < q_cap), alpha_l^(S m)
-  int32_t q_cap;       // power-table capacity (>= n_seg, >= 2)
-  uint32_t *sl_ctrl;   // control words of the STA/LTA object (epoch, counter)
-  int64_t nlta;
   double nsta_d, nlta_d;
-  float as, al;        // FP32 decay factors 1 - 1/nsta, 1 - 1/nlta
+  int64_t nlta;
+  float as, al;        // FP32 decay factors
   float kappa;         // nlta / nsta (cf = kappa * S / L in the scaled sums)
-
-  // look-back workspace of the launching object
-  double *rec;         // SOS records, then STA/LTA records
-  uint32_t *flags;     // [2][n_seg][n_grp]
-  uint32_t *ctrl;      // launch control words (tickets, done, epoch, error)
-  int32_t spin_limit;  // bounded wait (iterations) before flagging a timeout
 };
 
-// Dynamic LDS bytes of a forward workgroup with `waves` data waves.
-size_t fwd_lds_bytes(int K, int waves);
+// Dynamic LDS bytes of a forward workgroup.
+size_t fwd_lds_bytes(int K, int nw, int n_lev);
 
-// Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only;
-// `waves` data waves (<= kMaxWaves - 1) plus one carry wave per workgroup.
-hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, int waves,
-                      hipStream_t stream);
+// Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only.
+hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, hipStream_t stream);
+
+// Workgroups launched for a parameter set (groups rounded up to whole XCD runs).
+inline int fwd_grid(const FwdParams &p) {
+  const int run = 8 * p.xq;
+  return (p.n_grp + run - 1) / run * run;
+}
 
 }  // namespace filark

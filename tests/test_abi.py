@@ -80,7 +80,7 @@ def test_null_and_range_errors_without_gpu(F):
     assert L.filark_sos_process(vp(0), vp(0), vp(0), 4, 4, vp(0)) == F.EINVAL
     assert L.filark_stalta_process(vp(0), vp(0), vp(0), 4, 4, vp(0)) == F.EINVAL
     assert L.filark_sos_stalta_process(vp(0), vp(0), vp(0), vp(0), vp(0), 4, 4, vp(0)) == F.EINVAL
-    assert L.filark_tile_set(vp(0), 0, 64, 4, vp(0)) == F.EINVAL
+    assert L.filark_tile_set(vp(0), 0, 64, 4, 8, vp(0)) == F.EINVAL
     assert L.filark_sos_destroy(vp(0)) == F.OK
     assert L.filark_stalta_destroy(vp(0)) == F.OK
     sos = np.array([[1.0, 0.0, 0.0, 1.0, -0.5, 0.0]])

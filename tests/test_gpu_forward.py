@@ -213,19 +213,19 @@ def test_near_unit_circle_highpass(F):
 
 
 def test_run_to_run_reproducibility(F):
-    """The carry of a segment is composed along whichever predecessor records are
-    already published, so its FP64 rounding may differ between runs; outputs
-    may then differ by an FP32 ulp on rare samples, never more."""
+    """Carries never cross workgroups and every reduction has a fixed order,
+    so two runs give identical bits."""
     orc = _oracle()
     g = torch.Generator(device="cuda").manual_seed(10)
     x = torch.randn((6000, 500), generator=g, device="cuda", dtype=torch.float32)
     sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
     a = run_gpu_chunks(F, sos, x, [1500] * 4, 300, 3000, 1500.0)
     b = run_gpu_chunks(F, sos, x, [1500] * 4, 300, 3000, 1500.0)
-    for u, v in [(a[0], b[0]), (a[1], b[1])]:
-        assert_within_ulps(u, v)
-    za, zb = a[2].get_state(), b[2].get_state()
-    np.testing.assert_allclose(za, zb, rtol=1e-12, atol=1e-12 * np.abs(za).max())
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2].get_state(), b[2].get_state())
+    sa, ga = a[3].get_state()
+    sb, gb = b[3].get_state()
+    assert np.array_equal(sa, sb) and ga == gb == 6000
 
 
 def test_shape_errors(F):
@@ -242,19 +242,21 @@ def test_shape_errors(F):
 
 
 @pytest.mark.parametrize("block", [32, 64])
-@pytest.mark.parametrize("waves", [1, 2, 3, 4, 6, 8])
-def test_tile_shapes(F, block, waves):
-    """Every tile shape gives the oracle's result (ragged channels and time)."""
+@pytest.mark.parametrize("waves", [1, 3, 8])
+@pytest.mark.parametrize("group", [4, 8, 16, 64])
+def test_tile_shapes(F, block, waves, group):
+    """Every tile shape gives the oracle's result (ragged channels, chunks
+    shorter and longer than a window, which then runs as several launches)."""
     orc = _oracle()
-    g = torch.Generator(device="cuda").manual_seed(11 + block + waves)
+    g = torch.Generator(device="cuda").manual_seed(11 + block + waves + group)
     n_ch, splits = 131, [1, 700, 1999, 2]
     x = torch.randn((sum(splits), n_ch), generator=g, device="cuda", dtype=torch.float32)
     sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
     st = F.SOSState(sos, n_ch)
     sl = F.StaLtaState(30 / 1500.0, 300 / 1500.0, 1500.0, n_ch)
-    st.set_tile(block, waves)
-    sl.set_tile(block, waves)
-    assert st.tile() == (block, waves) and sl.tile() == (block, waves)
+    st.set_tile(block, waves, group)
+    sl.set_tile(block, waves, group)
+    assert st.tile() == (block, waves, group) and sl.tile() == (block, waves, group)
     ys, cfs, t0 = [], [], 0
     for n in splits:
         y, cf = F.sos_stalta_process(st, sl, x[t0:t0 + n].contiguous())
@@ -269,6 +271,9 @@ def test_tile_shapes(F, block, waves):
     assert max_rel_rms(torch.cat(ys).cpu().numpy(), yo) <= 1e-5
     assert max_rel_rms(torch.cat(cfs).cpu().numpy(), cfo) <= 1e-5
     np.testing.assert_allclose(st.get_state(), s.zi, rtol=1e-6, atol=1e-6 * np.abs(s.zi).max())
+    slst, gg = sl.get_state()
+    assert gg == sum(splits)
+    np.testing.assert_allclose(slst, s.st, rtol=1e-6)
 
 
 def test_tile_shape_errors(F):
@@ -276,11 +281,11 @@ def test_tile_shape_errors(F):
     sos = orc.butter_sos(4, "bandpass", 1.0, 50.0, 500.0)
     st = F.SOSState(sos, 64)
     sl = F.StaLtaState(0.1, 1.0, 500.0, 64)
-    for b, w in [(16, 4), (64, 0), (64, 9), (48, 2)]:
+    for b, w, gr in [(16, 4, 8), (64, 0, 8), (64, 9, 8), (48, 2, 8), (64, 2, 3), (64, 2, 128)]:
         with pytest.raises(F.FilarkError) as e:
-            st.set_tile(b, w)
+            st.set_tile(b, w, gr)
         assert e.value.status == F.EINVAL
-    st.set_tile(32, 2)
+    st.set_tile(32, 2, 8)
     with pytest.raises(F.FilarkError) as e:  # fused call needs equal shapes
         F.sos_stalta_process(st, sl, torch.zeros((10, 64), device="cuda"))
     assert e.value.status == F.EINVAL
