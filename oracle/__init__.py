@@ -66,13 +66,13 @@ def lib():
 
 
 def _register_grad(L):
-    if not hasattr(L, "oracle_sos_stalta_grad"):
-        return
     D = ctypes.POINTER(ctypes.c_double)
     I64 = ctypes.c_int64
-    L.oracle_sos_stalta_grad.argtypes = [D, ctypes.c_int, D, D, I64, I64, I64, I64, ctypes.c_int64,
-                                         D, D, D]
+    L.oracle_sos_stalta_grad.argtypes = [D, ctypes.c_int, D, D, I64, I64, I64, I64, I64, ctypes.c_double,
+                                         D, D, D, D, D, D]
     L.oracle_sos_stalta_grad.restype = None
+    L.oracle_sos_vjp.argtypes = [D, ctypes.c_int, D, D, I64, I64, D, D, D, D]
+    L.oracle_sos_vjp.restype = None
 
 
 def _ptr(a: np.ndarray):
@@ -158,3 +158,56 @@ class Stream:
             return y, None
         cf, self.st, self.g = stalta(y, self.nsta, self.nlta, self.st, self.g)
         return y, cf
+
+
+def stalta_grad(sos, x, tgt, nsta: int, nlta: int, scale: float, zi0=None, st0=None, g0: int = 0,
+                adj=None):
+    """Reverse-mode gradient of loss = scale * sum (cf - tgt)^2 over one chunk.
+
+    x, tgt: [n_t, n_ch].  zi0 [n_ch, n_sec, 2], st0 [n_ch, 2], g0: the forward
+    state at the chunk start (the checkpoint).  adj [n_ch, 2 n_sec + 2]: the
+    adjoint of the state after the chunk (zero after the record's end).
+    Returns (loss, gx [n_t, n_ch], gsos [n_sec, 5] for (b0, b1, b2, a1, a2),
+    adj_before [n_ch, 2 n_sec + 2]).
+    """
+    sos = _f64(sos)
+    x = _f64(x)
+    tgt = _f64(tgt)
+    n_t, n_ch = x.shape
+    n_sec = sos.shape[0]
+    z = np.zeros((n_ch, n_sec, 2)) if zi0 is None else _f64(zi0)
+    st = np.zeros((n_ch, 2)) if st0 is None else _f64(st0)
+    a = np.zeros((n_ch, 2 * n_sec + 2)) if adj is None else _f64(adj).copy()
+    gx = np.empty_like(x)
+    gsos = np.zeros((n_sec, 5))
+    loss = np.zeros(1)
+    lib().oracle_sos_stalta_grad(_ptr(sos), n_sec, _ptr(x), _ptr(tgt), n_ch, n_t, int(nsta), int(nlta),
+                                 int(g0), float(scale), _ptr(z), _ptr(st), _ptr(a), _ptr(gx), _ptr(gsos),
+                                 _ptr(loss))
+    return float(loss[0]), gx, gsos, a
+
+
+def sos_vjp(sos, x, gy, zi0=None, adjz=None):
+    """(dy/dx)^T gy and sum gy . dy/dtheta of the cascade over one chunk.
+
+    Returns (gx [n_t, n_ch], gsos [n_sec, 5], adjz_before [n_ch, n_sec, 2]).
+    """
+    sos = _f64(sos)
+    x = _f64(x)
+    gy = _f64(gy)
+    n_t, n_ch = x.shape
+    n_sec = sos.shape[0]
+    z = np.zeros((n_ch, n_sec, 2)) if zi0 is None else _f64(zi0)
+    a = np.zeros((n_ch, n_sec, 2)) if adjz is None else _f64(adjz).copy()
+    gx = np.empty_like(x)
+    gsos = np.zeros((n_sec, 5))
+    lib().oracle_sos_vjp(_ptr(sos), n_sec, _ptr(x), _ptr(gy), n_ch, n_t, _ptr(z), _ptr(a), _ptr(gx),
+                         _ptr(gsos))
+    return gx, gsos, a
+
+
+def stalta_loss(sos, x, tgt, nsta: int, nlta: int, scale: float) -> float:
+    """loss = scale * sum (cf - tgt)^2 of one record from the zero state (forward only)."""
+    y, _ = sos_filter(sos, x)
+    cf, _, _ = stalta(y, nsta, nlta)
+    return float(scale * np.sum((cf - _f64(tgt)) ** 2))

@@ -369,3 +369,189 @@ void oracle_stalta(const double *y, double *cf, int64_t n_ch, int64_t n_t,
   }
   *g0 = gstart + n_t;
 }
+
+/* ------------------------------------------------------------------------
+ * Reference gradient (reverse mode, written out by hand) of the chunk loss
+ *     loss = scale * sum_{t,c} (cf[t][c] - tgt[t][c])^2
+ * with respect to the input x and the normalised section coefficients
+ * (b0, b1, b2, a1, a2) of every section.  The paper gives no gradient; the
+ * derivative of the forward loops above is taken operation by operation, in
+ * reverse order:
+ *   STA/LTA at sample t, with q = 2 scale (cf - tgt) where cf is live
+ *   (g >= nlta and lta > 0), else 0, and (A, B) the adjoints of (sta, lta)
+ *   after sample t coming from later samples:
+ *       S = A + q / lta,   Lb = B - q sta / lta^2,   e_bar = cs S + cl Lb,
+ *       y_bar = 2 y e_bar,  then A <- (1 - cs) S,  B <- (1 - cl) Lb;
+ *   each section, last to first, given the adjoint y_bar of its output and
+ *   (u1, u2) of its delay pair after the sample:
+ *       from z2' = b2 v - a2 y:        gb2 += u2 v, v_bar  = b2 u2, ga2 -= u2 y, y_bar -= a2 u2
+ *       from z1' = b1 v - a1 y + z2:   gb1 += u1 v, v_bar += b1 u1, ga1 -= u1 y, y_bar -= a1 u1,
+ *                                      u2 <- u1
+ *       from y = b0 v + z1:            gb0 += y_bar v, v_bar += b0 y_bar, u1 <- y_bar
+ *   and v_bar is the output adjoint of the section before (x_bar for the
+ *   first).
+ * A chunk is one call: the forward state at its start (zi0, st0, g0) is the
+ * checkpoint, and adj[c] = (u1, u2 per section, A, B) carries the adjoint
+ * of the state after the chunk in and the adjoint of the state before it
+ * out, so chunks processed last-to-first give the one-shot gradient (the
+ * adjoint after the record's last sample is zero).
+ * gx [n_t][n_ch] is written; gsos [n_sec][5] and *loss are added to, in
+ * channel order (independent of the thread count).
+ * ---------------------------------------------------------------------- */
+static void coef_row(const double *r, double *b0, double *b1, double *b2, double *a1, double *a2) {
+  double a0 = r[3];
+  *b0 = r[0] / a0;
+  *b1 = r[1] / a0;
+  *b2 = r[2] / a0;
+  *a1 = r[4] / a0;
+  *a2 = r[5] / a0;
+}
+
+/* Reverse through the cascade at one sample. v[k] is the input of section k,
+ * v[n_sec] the cascade output; u[2k], u[2k+1] the adjoints of section k's
+ * delay pair after the sample (replaced by the adjoints before it); g[5k..]
+ * accumulates the coefficient gradients.  Returns the adjoint of x. */
+static double cascade_reverse(const double *sos, int n_sec, const double *v, double ybar, double *u,
+                              double *g) {
+  for (int k = n_sec - 1; k >= 0; --k) {
+    double b0, b1, b2, a1, a2;
+    coef_row(sos + 6 * k, &b0, &b1, &b2, &a1, &a2);
+    const double vin = v[k], yout = v[k + 1];
+    const double u1 = u[2 * k], u2 = u[2 * k + 1];
+    double yb = ybar;
+    double vb;
+    /* z2' = b2 v - a2 y */
+    g[5 * k + 2] += u2 * vin;
+    vb = b2 * u2;
+    g[5 * k + 4] -= u2 * yout;
+    yb -= a2 * u2;
+    /* z1' = b1 v - a1 y + z2 */
+    g[5 * k + 1] += u1 * vin;
+    vb += b1 * u1;
+    g[5 * k + 3] -= u1 * yout;
+    yb -= a1 * u1;
+    /* y = b0 v + z1 */
+    g[5 * k + 0] += yb * vin;
+    vb += b0 * yb;
+    u[2 * k] = yb;   /* adjoint of z1 before the sample */
+    u[2 * k + 1] = u1; /* adjoint of z2 before the sample */
+    ybar = vb;
+  }
+  return ybar;
+}
+
+void oracle_sos_stalta_grad(const double *sos, int n_sec, const double *x, const double *tgt,
+                            int64_t n_ch, int64_t n_t, int64_t nsta, int64_t nlta, int64_t g0,
+                            double scale, const double *zi0, const double *st0, double *adj,
+                            double *gx, double *gsos, double *loss) {
+  const double cs = 1.0 / (double)nsta, cl = 1.0 / (double)nlta;
+  const int na = 2 * n_sec + 2;
+  double *gch = (double *)calloc((size_t)n_ch * (5 * n_sec + 1), sizeof(double));
+#pragma omp parallel
+  {
+    /* per-thread tape of one channel: section inputs / output, sta, lta */
+    double *tv = (double *)malloc((size_t)n_t * (n_sec + 1) * sizeof(double));
+    double *ts = (double *)malloc((size_t)n_t * 2 * sizeof(double));
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < n_ch; ++c) {
+      double z[2 * 128];
+      for (int i = 0; i < 2 * n_sec; ++i) z[i] = zi0[c * 2 * n_sec + i];
+      double sta = st0[2 * c], lta = st0[2 * c + 1];
+      double *gc = gch + c * (5 * n_sec + 1);
+      for (int64_t t = 0; t < n_t; ++t) {
+        double v = x[t * n_ch + c];
+        double *row = tv + t * (n_sec + 1);
+        for (int k = 0; k < n_sec; ++k) {
+          double b0, b1, b2, a1, a2;
+          coef_row(sos + 6 * k, &b0, &b1, &b2, &a1, &a2);
+          row[k] = v;
+          double out = b0 * v + z[2 * k];
+          z[2 * k] = b1 * v - a1 * out + z[2 * k + 1];
+          z[2 * k + 1] = b2 * v - a2 * out;
+          v = out;
+        }
+        row[n_sec] = v;
+        double e = v * v;
+        sta = (1.0 - cs) * sta + cs * e;
+        lta = (1.0 - cl) * lta + cl * e;
+        ts[2 * t] = sta;
+        ts[2 * t + 1] = lta;
+      }
+      double u[2 * 128];
+      for (int i = 0; i < 2 * n_sec; ++i) u[i] = adj[c * na + i];
+      double A = adj[c * na + 2 * n_sec], B = adj[c * na + 2 * n_sec + 1];
+      double lsum = 0.0;
+      for (int64_t t = n_t - 1; t >= 0; --t) {
+        const double s = ts[2 * t], l = ts[2 * t + 1];
+        const int live = (g0 + t >= nlta && l > 0.0);
+        const double cf = live ? s / l : 0.0;
+        const double d = cf - tgt[t * n_ch + c];
+        lsum += scale * d * d;
+        const double q = live ? 2.0 * scale * d : 0.0;
+        const double S = A + (live ? q / l : 0.0);
+        const double Lb = B - (live ? q * s / (l * l) : 0.0);
+        const double ebar = cs * S + cl * Lb;
+        A = (1.0 - cs) * S;
+        B = (1.0 - cl) * Lb;
+        const double *row = tv + t * (n_sec + 1);
+        const double ybar = 2.0 * row[n_sec] * ebar;
+        gx[t * n_ch + c] = cascade_reverse(sos, n_sec, row, ybar, u, gc);
+      }
+      for (int i = 0; i < 2 * n_sec; ++i) adj[c * na + i] = u[i];
+      adj[c * na + 2 * n_sec] = A;
+      adj[c * na + 2 * n_sec + 1] = B;
+      gc[5 * n_sec] = lsum;
+    }
+    free(tv);
+    free(ts);
+  }
+  for (int64_t c = 0; c < n_ch; ++c) {
+    const double *gc = gch + c * (5 * n_sec + 1);
+    for (int i = 0; i < 5 * n_sec; ++i) gsos[i] += gc[i];
+    *loss += gc[5 * n_sec];
+  }
+  free(gch);
+}
+
+/* Vector-Jacobian product of the cascade alone over one chunk: given the
+ * adjoint gy [n_t][n_ch] of the filter output, gx = (d y / d x)^T gy and the
+ * coefficient gradients sum_t gy . d y / d theta (gsos [n_sec][5], added to).
+ * zi0 is the forward state at the chunk start; adjz [n_ch][n_sec][2] carries
+ * the delay-pair adjoints in (after the chunk) and out (before it). */
+void oracle_sos_vjp(const double *sos, int n_sec, const double *x, const double *gy, int64_t n_ch,
+                    int64_t n_t, const double *zi0, double *adjz, double *gx, double *gsos) {
+  double *gch = (double *)calloc((size_t)n_ch * 5 * n_sec, sizeof(double));
+#pragma omp parallel
+  {
+    double *tv = (double *)malloc((size_t)n_t * (n_sec + 1) * sizeof(double));
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < n_ch; ++c) {
+      double z[2 * 128];
+      for (int i = 0; i < 2 * n_sec; ++i) z[i] = zi0[c * 2 * n_sec + i];
+      for (int64_t t = 0; t < n_t; ++t) {
+        double v = x[t * n_ch + c];
+        double *row = tv + t * (n_sec + 1);
+        for (int k = 0; k < n_sec; ++k) {
+          double b0, b1, b2, a1, a2;
+          coef_row(sos + 6 * k, &b0, &b1, &b2, &a1, &a2);
+          row[k] = v;
+          double out = b0 * v + z[2 * k];
+          z[2 * k] = b1 * v - a1 * out + z[2 * k + 1];
+          z[2 * k + 1] = b2 * v - a2 * out;
+          v = out;
+        }
+        row[n_sec] = v;
+      }
+      double u[2 * 128];
+      for (int i = 0; i < 2 * n_sec; ++i) u[i] = adjz[c * 2 * n_sec + i];
+      double *gc = gch + c * 5 * n_sec;
+      for (int64_t t = n_t - 1; t >= 0; --t)
+        gx[t * n_ch + c] = cascade_reverse(sos, n_sec, tv + t * (n_sec + 1), gy[t * n_ch + c], u, gc);
+      for (int i = 0; i < 2 * n_sec; ++i) adjz[c * 2 * n_sec + i] = u[i];
+    }
+    free(tv);
+  }
+  for (int64_t c = 0; c < n_ch; ++c)
+    for (int i = 0; i < 5 * n_sec; ++i) gsos[i] += gch[c * 5 * n_sec + i];
+  free(gch);
+}
