@@ -61,8 +61,17 @@ typedef enum filark_btype {
   FILARK_BANDSTOP = 3
 } filark_btype;
 
-/* State kinds for filark_state_get / filark_state_set. */
-enum { FILARK_STATE_SOS = 0, FILARK_STATE_STALTA = 1 };
+/* State kinds for filark_state_get / _set / _save / _load / _bytes; the
+ * tile calls also take the adjoint-kernel kinds. */
+enum {
+  FILARK_STATE_SOS = 0,
+  FILARK_STATE_STALTA = 1,
+  FILARK_TILE_SOS_ADJOINT = 2,
+  FILARK_TILE_STALTA_ADJOINT = 3
+};
+
+/* Modes of filark_sos_stalta_adjoint. */
+enum { FILARK_ADJ_GRAD = 0, FILARK_ADJ_MSE = 1 };
 
 typedef struct filark_sos_state *filark_sos_t;
 typedef struct filark_stalta_state *filark_stalta_t;
@@ -164,16 +173,55 @@ filark_status filark_state_set(void *st, int kind, const void *host_buf, size_t 
 /*
  * Tile shape of a state object's kernels (a tuning knob; results do not
  * depend on it beyond FP64 rounding of the carries).  A workgroup of `waves`
- * waves owns `group` consecutive channels for the whole chunk and walks it in
- * windows of waves * 64 / group blocks of `block` samples per lane.
- *   block  32 or 64;  waves  1 .. 8;  group  4, 8, 16, 32 or 64.
- * Default 64 x 3 x 8 (windows of 1536 rows).  Both states passed to
- * filark_sos_stalta_process must have the same shape.  _set synchronises
- * `stream` and rebuilds the scan tables; kind as for filark_state_get.
- * FILARK_EINVAL for a shape outside the ranges above.
+ * waves owns `group` consecutive channels and covers a window of
+ * waves * 64 / group blocks of `block` samples per lane; longer chunks run
+ * window by window.
+ *   kind FILARK_STATE_SOS / _STALTA (forward): block 32 or 64, default 64 x 3 x 8;
+ *   kind FILARK_TILE_SOS_ADJOINT / _STALTA_ADJOINT: block 8 or 16, default 8 x 8 x 8;
+ *   waves 1 .. 8;  group 4, 8, 16, 32 or 64.
+ * The SOS and STA/LTA states used together must have equal shapes.  _set
+ * synchronises `stream` and rebuilds the scan tables.  FILARK_EINVAL for a
+ * shape outside the ranges above.
  */
 filark_status filark_tile_set(void *st, int kind, int block, int waves, int group, hipStream_t stream);
 filark_status filark_tile_get(const void *st, int kind, int *block, int *waves, int *group);
+
+/*
+ * Device-side checkpoints of a state (for the adjoint of a chunked run):
+ * _bytes gives the size of the opaque device image, _save copies the state
+ * into `dev_dst` and _load restores it from `dev_src` (device buffers of that
+ * size owned by the caller).  Both are asynchronous copies on `stream`.
+ */
+filark_status filark_state_bytes(const void *st, int kind, size_t *bytes);
+filark_status filark_state_save(const void *st, int kind, void *dev_dst, hipStream_t stream);
+filark_status filark_state_load(void *st, int kind, const void *dev_src, hipStream_t stream);
+
+/*
+ * Reverse-mode gradient of a loss on the fused path's characteristic
+ * function over one chunk (the adjoint of filark_sos_stalta_process: the
+ * time-reversed, transposed recurrences of the STA/LTA and of the cascade).
+ * The paper gives no gradient; this is the derivative of the forward
+ * operation defined above.
+ *   sos, sl   hold the forward state at the START of the chunk (restore the
+ *             chunk's checkpoint first); they are not modified.
+ *   x         device FP32 [n_t][n_ch], the chunk's input.
+ *   g         mode FILARK_ADJ_GRAD: dL/dcf [n_t][n_ch];
+ *             mode FILARK_ADJ_MSE:  the target cf, with
+ *             L = scale * sum (cf - target)^2 over the chunk.
+ *   gx        device FP32 [n_t][n_ch], receives dL/dx.
+ *   adj       device FP64 [2K + 2][n_ch]: the adjoint of the state after the
+ *             chunk on entry (zero after a record's last chunk), the adjoint
+ *             of the state before it on return; rows are (dL/dz1, dL/dz2) of
+ *             each section, then dL/dsta, dL/dlta.
+ *   gsos      device FP64 [K][5], dL/d(b0, b1, b2, a1, a2) of each section,
+ *             ADDED to (coefficients normalised by a0).
+ * Chunks of a record are processed last to first with their checkpoints,
+ * carrying adj.  Results are deterministic.  Asynchronous on `stream`; may
+ * allocate its workspace (window checkpoints) on first use.
+ */
+filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, const float *x,
+                                        const float *g, int mode, double scale, float *gx, double *adj,
+                                        double *gsos, int64_t n_ch, int64_t n_t, hipStream_t stream);
 
 /*
  * Synchronise `stream` and report an asynchronous HIP error of the work

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libfilark.so")
 
 OK, EINVAL, ESHAPE, ENOMEM, EHIP, EUNSTABLE, ETIMEOUT = range(7)
 BTYPES = {"lowpass": 0, "highpass": 1, "bandpass": 2, "bandstop": 3}
-STATE_SOS, STATE_STALTA = 0, 1
+STATE_SOS, STATE_STALTA, TILE_SOS_ADJOINT, TILE_STALTA_ADJOINT = 0, 1, 2, 3
+ADJ_GRAD, ADJ_MSE = 0, 1
 
 _lib = None
 
@@ -30,7 +31,8 @@ EXPORTS = (
     "filark_sos_design", "filark_sos_init", "filark_sos_process", "filark_stalta_init",
     "filark_stalta_process", "filark_sos_stalta_process", "filark_state_get", "filark_state_set",
     "filark_check", "filark_sos_destroy", "filark_stalta_destroy", "filark_last_error",
-    "filark_version", "filark_tile_set", "filark_tile_get",
+    "filark_version", "filark_tile_set", "filark_tile_get", "filark_state_bytes", "filark_state_save",
+    "filark_state_load", "filark_sos_stalta_adjoint",
 )
 
 
@@ -67,6 +69,11 @@ def lib():
     ip = ctypes.POINTER(ctypes.c_int)
     L.filark_tile_set.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
     L.filark_tile_get.argtypes = [vp, ctypes.c_int, ip, ip, ip]
+    L.filark_state_bytes.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+    L.filark_state_save.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.filark_state_load.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.filark_sos_stalta_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp, i64,
+                                            i64, vp]
     L.filark_sos_destroy.argtypes = [vp]
     L.filark_stalta_destroy.argtypes = [vp]
     for name in EXPORTS:
@@ -163,6 +170,35 @@ class SOSState:
         _check(lib().filark_tile_get(self._h, STATE_SOS, ctypes.byref(b), ctypes.byref(w), ctypes.byref(g)))
         return b.value, w.value, g.value
 
+    def set_adjoint_tile(self, block: int, waves: int, group: int = 8, stream=None):
+        _check(lib().filark_tile_set(self._h, TILE_SOS_ADJOINT, int(block), int(waves), int(group), _stream(stream)))
+
+    def adjoint_tile(self):
+        b, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().filark_tile_get(self._h, TILE_SOS_ADJOINT, ctypes.byref(b), ctypes.byref(w), ctypes.byref(g)))
+        return b.value, w.value, g.value
+
+    def state_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().filark_state_bytes(self._h, STATE_SOS, ctypes.byref(n)))
+        return n.value
+
+    def save(self, buf=None, stream=None):
+        """Copy the device state into `buf` (a CUDA uint8 tensor; allocated if None)."""
+        import torch
+
+        if buf is None:
+            buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device="cuda")
+        if not buf.is_cuda or buf.numel() * buf.element_size() < self.state_bytes():
+            raise FilarkError(EINVAL, "checkpoint buffer too small")
+        _check(lib().filark_state_save(self._h, STATE_SOS, ctypes.c_void_p(buf.data_ptr()), _stream(stream)))
+        return buf
+
+    def load(self, buf, stream=None):
+        if not buf.is_cuda or buf.numel() * buf.element_size() < self.state_bytes():
+            raise FilarkError(EINVAL, "checkpoint buffer too small")
+        _check(lib().filark_state_load(self._h, STATE_SOS, ctypes.c_void_p(buf.data_ptr()), _stream(stream)))
+
     def close(self):
         if self._h:
             lib().filark_sos_destroy(self._h)
@@ -224,6 +260,35 @@ class StaLtaState:
         _check(lib().filark_tile_get(self._h, STATE_STALTA, ctypes.byref(b), ctypes.byref(w), ctypes.byref(g)))
         return b.value, w.value, g.value
 
+    def set_adjoint_tile(self, block: int, waves: int, group: int = 8, stream=None):
+        _check(lib().filark_tile_set(self._h, TILE_STALTA_ADJOINT, int(block), int(waves), int(group), _stream(stream)))
+
+    def adjoint_tile(self):
+        b, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().filark_tile_get(self._h, TILE_STALTA_ADJOINT, ctypes.byref(b), ctypes.byref(w), ctypes.byref(g)))
+        return b.value, w.value, g.value
+
+    def state_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().filark_state_bytes(self._h, STATE_STALTA, ctypes.byref(n)))
+        return n.value
+
+    def save(self, buf=None, stream=None):
+        """Copy the device state into `buf` (a CUDA uint8 tensor; allocated if None)."""
+        import torch
+
+        if buf is None:
+            buf = torch.empty(self.state_bytes(), dtype=torch.uint8, device="cuda")
+        if not buf.is_cuda or buf.numel() * buf.element_size() < self.state_bytes():
+            raise FilarkError(EINVAL, "checkpoint buffer too small")
+        _check(lib().filark_state_save(self._h, STATE_STALTA, ctypes.c_void_p(buf.data_ptr()), _stream(stream)))
+        return buf
+
+    def load(self, buf, stream=None):
+        if not buf.is_cuda or buf.numel() * buf.element_size() < self.state_bytes():
+            raise FilarkError(EINVAL, "checkpoint buffer too small")
+        _check(lib().filark_state_load(self._h, STATE_STALTA, ctypes.c_void_p(buf.data_ptr()), _stream(stream)))
+
     def close(self):
         if self._h:
             lib().filark_stalta_destroy(self._h)
@@ -249,3 +314,32 @@ def sos_stalta_process(sos: SOSState, sl: StaLtaState, x, y=None, cf=None, write
     _check(lib().filark_sos_stalta_process(sos.handle, sl.handle, _dev_f32(x, "x"), yp, _dev_f32(cf, "cf"),
                                            x.shape[1], x.shape[0], _stream(stream)))
     return (y if write_y else None), cf
+
+
+def sos_stalta_adjoint(sos: SOSState, sl: StaLtaState, x, g, gx=None, adj=None, gsos=None, mode: str = "grad",
+                       scale: float = 1.0, stream=None):
+    """Adjoint of the fused path over one chunk (states hold the chunk-start
+    checkpoint).  mode "grad": g = dL/dcf; mode "mse": g = target cf and
+    L = scale * sum (cf - g)^2.  adj [2K+2, n_ch] float64 carries the adjoint
+    state (after the chunk in, before it out); gsos [K, 5] float64 is added to.
+    Returns (gx, adj, gsos)."""
+    import torch
+
+    n_t, n_ch = x.shape
+    K = sos.n_sec
+    if gx is None:
+        gx = torch.empty_like(x)
+    if adj is None:
+        adj = torch.zeros((2 * K + 2, n_ch), dtype=torch.float64, device=x.device)
+    if gsos is None:
+        gsos = torch.zeros((K, 5), dtype=torch.float64, device=x.device)
+    for t, name in ((adj, "adj"), (gsos, "gsos")):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise FilarkError(EINVAL, f"{name} must be a contiguous float64 CUDA tensor")
+    if adj.shape != (2 * K + 2, n_ch) or gsos.shape != (K, 5):
+        raise FilarkError(EINVAL, "adj must be [2K+2, n_ch] and gsos [K, 5]")
+    m = {"grad": ADJ_GRAD, "mse": ADJ_MSE}[mode]
+    _check(lib().filark_sos_stalta_adjoint(sos.handle, sl.handle, _dev_f32(x, "x"), _dev_f32(g, "g"), m,
+                                           float(scale), _dev_f32(gx, "gx"), ctypes.c_void_p(adj.data_ptr()),
+                                           ctypes.c_void_p(gsos.data_ptr()), n_ch, n_t, _stream(stream)))
+    return gx, adj, gsos

@@ -1,0 +1,471 @@
+// Adjoint kernel: gradient of a loss on the STA/LTA characteristic with
+// respect to the input and the section coefficients, one window of a chunk
+// per launch, windows and chunks taken last to first.
+//
+// The loss reaches x through cf = sta / lta, the two exponential averages of
+// e = y^2, and the DF2T cascade y = H x.  Reverse mode runs the forward
+// recurrences backwards in time (the time-reversed, transposed recurrence):
+//   STA/LTA   with (A, B) the adjoints of (sta, lta) after sample t,
+//             q = dL/dcf where cf is live (else 0),
+//               Sb = A + q / lta,  Lb = B - q sta / lta^2,
+//               ybar = 2 y (cs Sb + cl Lb),  A <- (1 - cs) Sb,  B <- (1 - cl) Lb;
+//   filter    the delay-pair adjoints u of each section, last section first:
+//               yb = ybar - a1 u1 - a2 u2,  vbar = b0 yb + b1 u1 + b2 u2,
+//               u1 <- yb,  u2 <- u1,
+//             vbar feeding the section before; the first section's vbar is
+//             dL/dx, and the coefficient gradients gather the products of
+//             these adjoints with the forward section inputs and outputs.
+// Both backward recurrences are linear in their state, so a window is
+// parallelised like the forward: each lane owns a block of L samples of one
+// channel, runs the block backwards from a zero end state (or, for the block
+// holding the window's last row, from the adjoint state handed in), the
+// blocks are combined by a reverse Hillis-Steele scan through LDS with the
+// transposed block transitions (A^L)^T and (1 - c)^L, and every lane reruns
+// its block from the exact end state.  The forward values the backward pass
+// needs (section outputs, the STA/LTA averages) are recomputed from the
+// window's checkpointed start state with the forward scan of fwd.hip; the
+// averages are walked backwards from their block-end values.
+//
+// Lanes past the window's last row, or past the last channel, hold zeros and
+// contribute nothing.  Coefficient gradients are summed in FP64 per lane, then
+// per wave by a fixed butterfly, per workgroup in wave order, and across
+// workgroups by a separate fixed-order pass: results do not depend on timing.
+#include "device.h"
+
+namespace filark {
+
+// LDS: exchanges [nw * 64][2] and [nw * 64][2K + 1], level matrices
+// [n_lev][2K][2K], carried filter state [64][2K + 1] and the per-wave
+// coefficient sums [nw][5K], all FP64.
+size_t adj_lds_bytes(int K, int nw, int n_lev) {
+  const int NS = 2 * K, NSP = NS + 1;
+  return ((size_t)nw * kWave * (NSP + 2) + (size_t)n_lev * NS * NS + (size_t)kWave * NSP +
+          (size_t)nw * 5 * K) *
+         sizeof(double);
+}
+
+namespace {
+
+using namespace dev;
+typedef const FILARK_CONST AdjParams *aparams_t;
+__device__ __forceinline__ aparams_t aparams() { return dev::kparams<AdjParams>(); }
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) {
+  const int lo = __builtin_amdgcn_ds_bpermute(((threadIdx.x & 63) ^ m) << 2,
+                                              (int)(__builtin_bit_cast(uint64_t, v) & 0xffffffffu));
+  const int hi = __builtin_amdgcn_ds_bpermute(((threadIdx.x & 63) ^ m) << 2,
+                                              (int)(__builtin_bit_cast(uint64_t, v) >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Backward step of the STA/LTA at one row: (A, B) -> adjoints before the row,
+// (S, Lg) -> the scaled sums before the row; returns ybar of the row.
+struct SlBack {
+  double cs, cl, asd, ald, ias, ial, scale;
+  int64_t nlta;
+  int mode;
+  __device__ __forceinline__ double step(double &A, double &B, double &S, double &Lg, float yf,
+                                         float gq, int64_t gidx) const {
+    const double sta = S * cs, lta = Lg * cl;
+    const bool live = gidx >= nlta && lta > 0.0;
+    const double rl = live ? 1.0 / lta : 0.0;
+    const double cf = sta * rl;
+    const double q = live ? (mode ? 2.0 * scale * (cf - (double)gq) : (double)gq) : 0.0;
+    const double Sb = fma(q, rl, A);
+    const double Lb = fma(-q * cf, rl, B);
+    const double yd = (double)yf;
+    const double e = yd * yd;
+    const double ybar = 2.0 * yd * fma(cs, Sb, cl * Lb);
+    A = asd * Sb;
+    B = ald * Lb;
+    S = (S - e) * ias;
+    Lg = (Lg - e) * ial;
+    return ybar;
+  }
+};
+
+template <int K, int L>
+__global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
+  constexpr int NS = 2 * K, NSP = NS + 1, NC = 5 * K;
+  extern __shared__ double lds[];
+  aparams_t p = aparams();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = uniform(threadIdx.x / kWave);
+  const int NW = p->nw;
+  const int cwl = p->cw_log2;
+  const int CW = 1 << cwl, R = kWave >> cwl, NB = NW * R;
+  const int g = group_of(p->xq);
+  if (g >= p->n_grp) return;  // whole workgroup, before any barrier
+  const int r = lane >> cwl, cl = lane & (CW - 1);
+  const int b = w * R + r;
+  const int my = w * kWave + lane;
+  const int64_t n_ch = p->n_ch;
+  const int64_t c = (int64_t)g * CW + cl;
+  const bool cval = c < n_ch;
+  double *xsl = lds;                       // [NW * 64][2]
+  double *xch = xsl + 2 * NW * kWave;      // [NW * 64][NSP]
+  double *pw = xch + NW * kWave * NSP;     // [n_lev][NS][NS]
+  double *zc = pw + p->n_lev * NS * NS;    // [CW][NSP]
+  double *wsum = zc + kWave * NSP;         // [NW][NC]
+  double *xme = xch + my * NSP;
+  {
+    const int n = p->n_lev * NS * NS;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) pw[k] = p->Pw[k];
+    if (b == 0) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) zc[cl * NSP + i] = cval ? p->zs0[i * n_ch + c] : 0.0;
+    }
+  }
+  const int n_t = p->n_t;
+  const int b_end = (n_t - 1) / L;  // block holding the window's last row
+  const int64_t row0 = (int64_t)b * L;
+  const int nv = (int)(row0 >= n_t ? 0 : (n_t - row0 >= L ? L : n_t - row0));
+  const uint32_t rowb = (uint32_t)n_ch * 4u;
+  const uint32_t vo = cval ? (uint32_t)((row0 * n_ch + c) * 4) : kOffInvalid;
+
+  float xv[L], gv[L];
+  {
+    const __amdgpu_buffer_rsrc_t rx = rsrc(aparams()->x, aparams()->range);
+    const __amdgpu_buffer_rsrc_t rg = rsrc(aparams()->g, aparams()->range);
+    const uint32_t rb = fresh(rowb);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      xv[j] = buf_ld(rx, vo + (uint32_t)j * rb);
+      gv[j] = buf_ld(rg, vo + (uint32_t)j * rb);
+      if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  __syncthreads();  // level matrices and the checkpointed state are in LDS
+
+  // ---------------- forward recompute: filter ----------------
+  float yk[K][L];                 // output of section k at each row of the block
+  double s_loc = 0.0, l_loc = 0.0;  // STA/LTA sums from zero over the block's valid rows
+  {
+    cdouble *G = as_const(aparams()->G);
+    double a[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) a[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const double xd = (double)xv[j];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) a[i] = fma(G[j * NS + i], xd, a[i]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (b == 0) {
+      double z0[NS];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) z0[i] = zc[cl * NSP + i];
+      mv_acc<NS>(pw, z0, a);
+    }
+    int lev = 0;
+    for (int d = 1; d < NB; d <<= 1, ++lev) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) xme[i] = a[i];
+      __syncthreads();
+      if (b >= d) {
+        const double *src = xme - d * CW * NSP;
+        double t[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) t[i] = src[i];
+        mv_acc<NS>(pw + lev * NS * NS, t, a);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) xme[i] = a[i];
+    __syncthreads();
+    double z[NS];
+    {
+      const double *src = b == 0 ? zc + cl * NSP : xme - CW * NSP;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) z[i] = src[i];
+    }
+    __syncthreads();  // the exchange is reused below
+    aparams_t q = aparams();
+    cdouble *coef = as_const(q->coef);
+    const double asd = q->asd, ald = q->ald;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      double v = (double)xv[j];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const double yy = fma(coef[5 * k + 0], v, z[2 * k]);
+        z[2 * k] = fma(coef[5 * k + 3], yy, fma(coef[5 * k + 1], v, z[2 * k + 1]));
+        z[2 * k + 1] = fma(coef[5 * k + 4], yy, coef[5 * k + 2] * v);
+        yk[k][j] = (float)yy;
+        v = yy;
+      }
+      // sums from the rounded output, the value the backward pass sees
+      const double yd = (double)yk[K - 1][j];
+      const double e = yd * yd;
+      if (j < nv) {
+        s_loc = fma(asd, s_loc, e);
+        l_loc = fma(ald, l_loc, e);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+
+  // ---------------- forward recompute: STA/LTA sums at block ends ----------------
+  int64_t g0 = 0;
+  double Se, Le;  // scaled sums after the block's last valid row
+  {
+    aparams_t q = aparams();
+    double S0 = 0.0, L0 = 0.0;
+    if (cval) {
+      g0 = q->cnt0[c];
+      if (b == 0) {
+        S0 = q->sl0[c] / q->cs;
+        L0 = q->sl0[n_ch + c] / q->cl;
+      }
+    }
+    cdouble *dp = as_const(q->dpow);
+    double s = s_loc, l = l_loc;
+    if (b == 0) {
+      s = fma(dp[0], S0, s);
+      l = fma(dp[1], L0, l);
+    }
+    int lev = 0;
+    for (int d = 1; d < NB; d <<= 1, ++lev) {
+      xsl[2 * my] = s;
+      xsl[2 * my + 1] = l;
+      __syncthreads();
+      if (b >= d) {
+        s = fma(dp[2 * lev], xsl[2 * (my - d * CW)], s);
+        l = fma(dp[2 * lev + 1], xsl[2 * (my - d * CW) + 1], l);
+      }
+      __syncthreads();
+    }
+    xsl[2 * my] = s;
+    xsl[2 * my + 1] = l;
+    __syncthreads();
+    double Sin = S0, Lin = L0;
+    if (b > 0) {
+      Sin = xsl[2 * (my - CW)];
+      Lin = xsl[2 * (my - CW) + 1];
+    }
+    __syncthreads();
+    // through this block's nv valid rows (fewer than L only at the window end)
+    cdouble *rp = as_const(q->dpow) + 2 * (q->n_lev + nv);
+    Se = fma(rp[0], Sin, s_loc);
+    Le = fma(rp[1], Lin, l_loc);
+  }
+
+  // ---------------- adjoint: STA/LTA ----------------
+  float yb[L];  // dL/dy of the cascade output at each row
+  {
+    aparams_t q = aparams();
+    SlBack sb{q->cs, q->cl, q->asd, q->ald, q->ias, q->ial, q->scale, q->nlta, q->mode};
+    double A = 0.0, B = 0.0;
+    if (b == b_end && cval) {
+      A = q->adj[NS * n_ch + c];
+      B = q->adj[(NS + 1) * n_ch + c];
+    }
+    {  // from the block end to its start, from zero (or the handed-in state)
+      double S = Se, Lg = Le;
+#pragma unroll
+      for (int j = L - 1; j >= 0; --j) {
+        if (j < nv) sb.step(A, B, S, Lg, yk[K - 1][j], gv[j], g0 + row0 + j);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    cdouble *dp = as_const(q->dpow);
+    int lev = 0;
+    for (int d = 1; d < NB; d <<= 1, ++lev) {
+      xsl[2 * my] = A;
+      xsl[2 * my + 1] = B;
+      __syncthreads();
+      if (b + d < NB) {
+        A = fma(dp[2 * lev], xsl[2 * (my + d * CW)], A);
+        B = fma(dp[2 * lev + 1], xsl[2 * (my + d * CW) + 1], B);
+      }
+      __syncthreads();
+    }
+    xsl[2 * my] = A;
+    xsl[2 * my + 1] = B;
+    __syncthreads();
+    // exact adjoint after the block: the next block's start, or the
+    // handed-in state for the block holding the last row
+    double Ax = 0.0, Bx = 0.0;
+    if (b < b_end) {
+      Ax = xsl[2 * (my + CW)];
+      Bx = xsl[2 * (my + CW) + 1];
+    } else if (b == b_end && cval) {
+      Ax = q->adj[NS * n_ch + c];
+      Bx = q->adj[(NS + 1) * n_ch + c];
+    }
+    __syncthreads();
+    double S = Se, Lg = Le;
+#pragma unroll
+    for (int j = L - 1; j >= 0; --j) {
+      float v = 0.0f;
+      if (j < nv) v = (float)sb.step(Ax, Bx, S, Lg, yk[K - 1][j], gv[j], g0 + row0 + j);
+      yb[j] = v;
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (b == 0 && cval) {
+      // adjoint of (sta, lta) before the window; the filter part follows
+      xsl[2 * my] = Ax;
+      xsl[2 * my + 1] = Bx;
+    }
+  }
+
+  // ---------------- adjoint: filter ----------------
+  {
+    aparams_t q = aparams();
+    cdouble *coef = as_const(q->coef);
+    double u[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) u[i] = (b == b_end && cval) ? q->adj[i * n_ch + c] : 0.0;
+    // local pass: delay-pair adjoints at the block start (the table holds
+    // -a1, -a2, so ys is ybar - a1 u1 - a2 u2)
+#pragma unroll
+    for (int j = L - 1; j >= 0; --j) {
+      if (j < nv) {
+        double ybar = (double)yb[j];
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+          const double u1 = u[2 * k], u2 = u[2 * k + 1];
+          const double ys = fma(coef[5 * k + 4], u2, fma(coef[5 * k + 3], u1, ybar));
+          ybar = fma(coef[5 * k + 2], u2, fma(coef[5 * k + 1], u1, coef[5 * k + 0] * ys));
+          u[2 * k] = ys;
+          u[2 * k + 1] = u1;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    int lev = 0;
+    for (int d = 1; d < NB; d <<= 1, ++lev) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) xme[i] = u[i];
+      __syncthreads();
+      if (b + d < NB) {
+        const double *src = xme + d * CW * NSP;
+        double t[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) t[i] = src[i];
+        mtv_acc<NS>(pw + lev * NS * NS, t, u);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) xme[i] = u[i];
+    __syncthreads();
+    if (b < b_end) {
+      const double *src = xme + CW * NSP;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) u[i] = src[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) u[i] = (b == b_end && cval) ? q->adj[i * n_ch + c] : 0.0;
+    }
+    __syncthreads();  // the adjoint state is overwritten below
+
+    // rerun from the exact end state: dL/dx and the coefficient gradients
+    double gc[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) gc[i] = 0.0;
+    const __amdgpu_buffer_rsrc_t rgx = rsrc(q->gx, q->range);
+    const uint32_t rb = fresh(rowb);
+#pragma unroll
+    for (int j = L - 1; j >= 0; --j) {
+      double ybar = (double)yb[j];
+      if (j < nv) {
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+          const double vin = k == 0 ? (double)xv[j] : (double)yk[k - 1][j];
+          const double yout = (double)yk[k][j];
+          const double u1 = u[2 * k], u2 = u[2 * k + 1];
+          const double ys = fma(coef[5 * k + 4], u2, fma(coef[5 * k + 3], u1, ybar));
+          gc[5 * k + 0] = fma(ys, vin, gc[5 * k + 0]);
+          gc[5 * k + 1] = fma(u1, vin, gc[5 * k + 1]);
+          gc[5 * k + 2] = fma(u2, vin, gc[5 * k + 2]);
+          gc[5 * k + 3] = fma(-u1, yout, gc[5 * k + 3]);
+          gc[5 * k + 4] = fma(-u2, yout, gc[5 * k + 4]);
+          ybar = fma(coef[5 * k + 2], u2, fma(coef[5 * k + 1], u1, coef[5 * k + 0] * ys));
+          u[2 * k] = ys;
+          u[2 * k + 1] = u1;
+        }
+      }
+      buf_st(rgx, vo + (uint32_t)j * rb, (float)ybar);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (b == 0 && cval) {  // the adjoint state before the window
+      double *adj = q->adj;
+#pragma unroll
+      for (int i = 0; i < NS; ++i) adj[i * n_ch + c] = u[i];
+      adj[NS * n_ch + c] = xsl[2 * my];
+      adj[(NS + 1) * n_ch + c] = xsl[2 * my + 1];
+    }
+
+    // coefficient gradients: wave butterfly, then the waves in order
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      double v = gc[i];
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+      if (lane == 0) wsum[w * NC + i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+      double s = 0.0;
+      for (int v = 0; v < NW; ++v) s += wsum[v * NC + threadIdx.x];
+      double *gp = aparams()->gpart + (size_t)g * NC + threadIdx.x;
+      *gp += s;
+    }
+  }
+}
+
+template <int K, int L>
+hipError_t launch_one(const AdjParams &p, hipStream_t stream) {
+  const size_t lds = adj_lds_bytes(K, p.nw, p.n_lev);
+  hipLaunchKernelGGL((adj_kernel<K, L>), dim3((unsigned)grid_for(p.n_grp, p.xq)),
+                     dim3((unsigned)(p.nw * kWave)), lds, stream, p);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_l(const AdjParams &p, int K, hipStream_t stream) {
+  switch (K) {
+    case 1: return launch_one<1, L>(p, stream);
+    case 2: return launch_one<2, L>(p, stream);
+    case 3: return launch_one<3, L>(p, stream);
+    case 4: return launch_one<4, L>(p, stream);
+    case 5: return launch_one<5, L>(p, stream);
+    case 6: return launch_one<6, L>(p, stream);
+    case 7: return launch_one<7, L>(p, stream);
+    case 8: return launch_one<8, L>(p, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// gsos[i] += sum over groups, in group order; gpart is cleared.
+__global__ void __launch_bounds__(256) adj_reduce_kernel(double *gpart, int n_grp, int n5, double *gsos) {
+  const int i = (int)threadIdx.x;
+  if (i >= n5) return;
+  double s = 0.0;
+  for (int g = 0; g < n_grp; ++g) {
+    s += gpart[(size_t)g * n5 + i];
+    gpart[(size_t)g * n5 + i] = 0.0;
+  }
+  gsos[i] += s;
+}
+
+}  // namespace
+
+hipError_t launch_adj(const AdjParams &p, int K, int L, hipStream_t stream) {
+  if (p.nw < 1 || p.nw > kMaxWaves || p.n_t < 1 || p.n_lev < 1 || p.n_lev > kMaxLevels)
+    return hipErrorInvalidValue;
+  if (L == 8) return launch_l<8>(p, K, stream);
+  if (L == 16) return launch_l<16>(p, K, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_reduce(double *gpart, int n_grp, int n5, double *gsos, hipStream_t stream) {
+  if (n5 < 1 || n5 > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(256), 0, stream, gpart, n_grp, n5, gsos);
+  return hipGetLastError();
+}
+
+}  // namespace filark

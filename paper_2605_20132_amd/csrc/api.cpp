@@ -148,27 +148,50 @@ int current_device() {
 
 }  // namespace
 
+// Scan tables of one tile shape: coef [K][5] = b0 b1 b2 -a1 -a2 |
+// G [L][2K] = A^(L-1-j) B | Pw [levels][2K][2K] = A^(L 2^k) (filter), or
+// [levels][2] = (as, al)^(L 2^k) then [L + 1][2] = (as, al)^m (STA/LTA).
+struct Tables {
+  Tile tile;
+  double *d = nullptr;
+  size_t off_G = 0, off_P = 0;
+};
+
 struct filark_sos_state {
   int device = 0;
   int64_t n_ch = 0;
   Cascade cas;
-  Tile tile;
   double *d_state = nullptr;  // [2K][n_ch]
-  double *d_tab = nullptr;    // coef | G | Pw
-  size_t off_G = 0, off_P = 0;
+  Tables fwd;                 // forward kernel
+  Tables adj;                 // adjoint kernel
+  // adjoint workspace: window checkpoints and per-group coefficient sums
+  double *d_ck = nullptr;
+  size_t ck_bytes = 0;
+  double *d_gpart = nullptr;
+  size_t gpart_bytes = 0;
 };
 
 struct filark_stalta_state {
   int device = 0;
   int64_t n_ch = 0;
   int64_t nsta = 0, nlta = 0;
-  Tile tile;
   double *d_state = nullptr;  // [2][n_ch] (sta, lta)
   int64_t *d_cnt = nullptr;   // [n_ch] global sample counter
-  double *d_tab = nullptr;    // decay powers
+  Tables fwd;
+  Tables adj;
 };
 
 namespace {
+
+// Default adjoint tile: 8-sample blocks, 8 waves, groups of 8 channels
+// (windows of 512 rows).
+Tile default_adj_tile() {
+  Tile t;
+  t.block = 8;
+  t.waves = 8;
+  t.group = 8;
+  return t;
+}
 
 filark_status upload(double **dst, const std::vector<double> &tab, hipStream_t stream) {
   if (*dst) {
@@ -182,40 +205,38 @@ filark_status upload(double **dst, const std::vector<double> &tab, hipStream_t s
   return FILARK_OK;
 }
 
-// coef [K][5] = b0 b1 b2 -a1 -a2 | G [L][2K] = A^(L-1-j) B | Pw [levels][2K][2K] = A^(L 2^k)
-filark_status sos_tables(filark_sos_state *st, hipStream_t stream) {
-  const int K = st->cas.K, n = 2 * K, L = st->tile.block;
+filark_status sos_tables(const Cascade &cas, Tables &tb, hipStream_t stream) {
+  const int K = cas.K, n = 2 * K, L = tb.tile.block;
   Mat A;
   std::vector<double> B;
-  cascade_matrices(st->cas, A, B);
+  cascade_matrices(cas, A, B);
   std::vector<double> tab;
   for (int k = 0; k < K; ++k) {
-    const double *r = st->cas.c[k];
+    const double *r = cas.c[k];
     tab.insert(tab.end(), {r[0], r[1], r[2], -r[3], -r[4]});
   }
   while (tab.size() % 8) tab.push_back(0.0);
-  st->off_G = tab.size();
+  tb.off_G = tab.size();
   std::vector<std::vector<double>> G(L);
   G[L - 1] = B;
   for (int j = L - 2; j >= 0; --j) G[j] = matvec(A, G[j + 1], n);
   for (int j = 0; j < L; ++j) tab.insert(tab.end(), G[j].begin(), G[j].end());
   while (tab.size() % 8) tab.push_back(0.0);
-  st->off_P = tab.size();
+  tb.off_P = tab.size();
   Mat P = identity(n);
   for (int j = 0; j < L; ++j) P = matmul(A, P, n);
-  for (int k = 0; k < st->tile.levels(); ++k) {
+  for (int k = 0; k < tb.tile.levels(); ++k) {
     tab.insert(tab.end(), P.begin(), P.end());
     P = matmul(P, P, n);
   }
-  return upload(&st->d_tab, tab, stream);
+  return upload(&tb.d, tab, stream);
 }
 
-// [levels][2] = (as, al)^(L 2^k), then [L + 1][2] = (as, al)^m, as = 1 - 1/nsta, al = 1 - 1/nlta
-filark_status stalta_tables(filark_stalta_state *st, hipStream_t stream) {
-  const int L = st->tile.block;
-  const double as = 1.0 - 1.0 / (double)st->nsta, al = 1.0 - 1.0 / (double)st->nlta;
+filark_status stalta_tables(int64_t nsta, int64_t nlta, Tables &tb, hipStream_t stream) {
+  const int L = tb.tile.block;
+  const double as = 1.0 - 1.0 / (double)nsta, al = 1.0 - 1.0 / (double)nlta;
   std::vector<double> tab;
-  for (int k = 0; k < st->tile.levels(); ++k) {
+  for (int k = 0; k < tb.tile.levels(); ++k) {
     const double e = (double)L * std::ldexp(1.0, k);
     tab.push_back(std::pow(as, e));
     tab.push_back(std::pow(al, e));
@@ -224,69 +245,58 @@ filark_status stalta_tables(filark_stalta_state *st, hipStream_t stream) {
     tab.push_back(std::pow(as, (double)m));
     tab.push_back(std::pow(al, (double)m));
   }
-  return upload(&st->d_tab, tab, stream);
+  return upload(&tb.d, tab, stream);
 }
 
-// Shared launch path of the three processing entry points.
-filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const float *in,
-                          float *y, float *cf, int64_t n_ch, int64_t n_t, hipStream_t stream) {
-  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
-  if (n_ch < 1) return fail(FILARK_EINVAL, "n_ch must be >= 1");
-  if (sos && sos->n_ch != n_ch)
-    return fail(FILARK_ESHAPE, "n_ch %lld differs from the SOS state's %lld", (long long)n_ch,
-                (long long)sos->n_ch);
-  if (sl && sl->n_ch != n_ch)
-    return fail(FILARK_ESHAPE, "n_ch %lld differs from the STA/LTA state's %lld", (long long)n_ch,
-                (long long)sl->n_ch);
-  if (n_t == 0) return FILARK_OK;
-  if (!in) return fail(FILARK_EINVAL, "null input pointer");
-  if (sos && !sl && !y) return fail(FILARK_EINVAL, "null output pointer");
-  if (sl && !cf) return fail(FILARK_EINVAL, "null cf pointer");
-  if (y && cf && (const void *)y == (const void *)cf) return fail(FILARK_EINVAL, "y and cf must differ");
-  const Tile t = sos ? sos->tile : sl->tile;
-  if (sos && sl && !(sos->tile == sl->tile))
-    return fail(FILARK_EINVAL, "tile shapes of the states differ (set both with filark_tile_set)");
-  // A launch covers one window of rows; longer chunks run as consecutive
-  // launches on the stream, the state carrying through device memory.  Byte
-  // offsets within a launch are 32-bit: the window's padded extent must stay
-  // below 2^31 bytes.
-  const uint64_t rowb = (uint64_t)n_ch * 4u;
-  const int64_t rows = t.window();
-  if ((uint64_t)rows * rowb > 0x7fffffffull)
-    return fail(FILARK_EINVAL, "n_ch %lld too large for a %d-row window (at most %lld channels)",
-                (long long)n_ch, (int)rows, (long long)(0x7fffffffull / (uint64_t)rows / 4u));
-  const int K = sos ? sos->cas.K : 0;
-
-  int prev_dev = current_device();
-  const int dev = sos ? sos->device : sl->device;
+filark_status check_lds(size_t lds, const Tile &t, int K, int dev) {
   int lds_max = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  const size_t lds = fwd_lds_bytes(K, t.waves, t.levels());
   if (lds > (size_t)lds_max)
     return fail(FILARK_EINVAL, "tile %dx%dx%d needs %zu bytes of LDS for %d sections (device limit %d)",
                 t.block, t.waves, t.group, lds, K, lds_max);
-  if (prev_dev != dev) HIP_TRY(hipSetDevice(dev));
+  return FILARK_OK;
+}
 
+int log2_exact(int v) {
+  int k = 0;
+  while ((1 << k) < v) ++k;
+  return k;
+}
+
+// Rows per launch of a tile, or 0 if a window's padded extent would reach
+// 2^31 bytes (byte offsets within a launch are 32-bit).
+int64_t launch_rows(const Tile &t, int64_t n_ch) {
+  const uint64_t rows = (uint64_t)t.window();
+  return rows * (uint64_t)n_ch * 4u > 0x7fffffffull ? 0 : (int64_t)rows;
+}
+
+// Forward launches over n_t rows from `in`, one window each, with the state
+// at (zs, sl, cnt) updated in place.  y / cf may be null; with neither (and
+// `states_only`) nothing but the state is written.
+hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_state *sl, const Tile &t,
+                            double *zs, double *slst, int64_t *cnt, const float *in, float *y, float *cf,
+                            bool states_only, int64_t n_ch, int64_t n_t, hipStream_t stream) {
+  const uint64_t rowb = (uint64_t)n_ch * 4u;
+  const int64_t rows = launch_rows(t, n_ch);
+  const int K = sos ? sos->cas.K : 0;
   FwdParams p;
   std::memset(&p, 0, sizeof p);
   p.n_ch = n_ch;
-  int cwl = 0;
-  while ((1 << cwl) < t.group) ++cwl;
-  p.cw_log2 = cwl;
+  p.cw_log2 = log2_exact(t.group);
   p.nw = t.waves;
   p.n_grp = (int)((n_ch + t.group - 1) / t.group);
   p.xq = std::max(1, 32 / t.group);  // groups sharing one 128-byte line
   p.n_lev = t.levels();
   if (sos) {
-    p.zs = sos->d_state;
-    p.coef = sos->d_tab;
-    p.G = sos->d_tab + sos->off_G;
-    p.Pw = sos->d_tab + sos->off_P;
+    p.zs = zs;
+    p.coef = sos->fwd.d;
+    p.G = sos->fwd.d + sos->fwd.off_G;
+    p.Pw = sos->fwd.d + sos->fwd.off_P;
   }
   if (sl) {
-    p.sl = sl->d_state;
-    p.cnt = sl->d_cnt;
-    p.dpow = sl->d_tab;
+    p.sl = slst;
+    p.cnt = cnt;
+    p.dpow = sl->fwd.d;
     p.nlta = sl->nlta;
     p.nsta_d = (double)sl->nsta;
     p.nlta_d = (double)sl->nlta;
@@ -305,15 +315,62 @@ filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const 
     p.cf = cf ? cf + off : nullptr;
     p.n_t = (int32_t)nt;
     p.range = (int32_t)((uint64_t)nt * rowb);
-    e = launch_fwd(p, K, t.block, sl != nullptr, sl == nullptr || y != nullptr, stream);
+    p.out_range = states_only ? 0 : p.range;
+    e = launch_fwd(p, K, t.block, sl != nullptr, !states_only && (sl == nullptr || y != nullptr), stream);
   }
+  return e;
+}
+
+// Shared launch path of the three processing entry points.
+filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const float *in,
+                          float *y, float *cf, int64_t n_ch, int64_t n_t, hipStream_t stream) {
+  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
+  if (n_ch < 1) return fail(FILARK_EINVAL, "n_ch must be >= 1");
+  if (sos && sos->n_ch != n_ch)
+    return fail(FILARK_ESHAPE, "n_ch %lld differs from the SOS state's %lld", (long long)n_ch,
+                (long long)sos->n_ch);
+  if (sl && sl->n_ch != n_ch)
+    return fail(FILARK_ESHAPE, "n_ch %lld differs from the STA/LTA state's %lld", (long long)n_ch,
+                (long long)sl->n_ch);
+  if (n_t == 0) return FILARK_OK;
+  if (!in) return fail(FILARK_EINVAL, "null input pointer");
+  if (sos && !sl && !y) return fail(FILARK_EINVAL, "null output pointer");
+  if (sl && !cf) return fail(FILARK_EINVAL, "null cf pointer");
+  if (y && cf && (const void *)y == (const void *)cf) return fail(FILARK_EINVAL, "y and cf must differ");
+  const Tile t = sos ? sos->fwd.tile : sl->fwd.tile;
+  if (sos && sl && !(sos->fwd.tile == sl->fwd.tile))
+    return fail(FILARK_EINVAL, "tile shapes of the states differ (set both with filark_tile_set)");
+  if (launch_rows(t, n_ch) == 0)
+    return fail(FILARK_EINVAL, "n_ch %lld too large for a %d-row window (at most %lld channels)",
+                (long long)n_ch, t.window(), (long long)(0x7fffffffull / (uint64_t)t.window() / 4u));
+  const int K = sos ? sos->cas.K : 0;
+  const int dev = sos ? sos->device : sl->device;
+  filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels()), t, K, dev);
+  if (rc != FILARK_OK) return rc;
+  const int prev_dev = current_device();
+  if (prev_dev != dev) HIP_TRY(hipSetDevice(dev));
+  hipError_t e = forward_launches(sos, sl, t, sos ? sos->d_state : nullptr, sl ? sl->d_state : nullptr,
+                                  sl ? sl->d_cnt : nullptr, in, y, cf, false, n_ch, n_t, stream);
   if (prev_dev != dev) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
   return FILARK_OK;
 }
 
-filark_status check_tile(int block, int waves, int group) {
-  if (block != 32 && block != 64) return fail(FILARK_EINVAL, "block must be 32 or 64");
+filark_status grow(double **buf, size_t *have, size_t need, hipStream_t stream) {
+  if (*buf && *have >= need) return FILARK_OK;
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (*buf) (void)hipFree(*buf);
+  *buf = nullptr;
+  *have = 0;
+  HIP_TRY(hipMalloc(buf, need));
+  HIP_TRY(hipMemsetAsync(*buf, 0, need, stream));
+  *have = need;
+  return FILARK_OK;
+}
+
+filark_status check_tile(int block, int waves, int group, bool adjoint) {
+  if (adjoint ? (block != 8 && block != 16) : (block != 32 && block != 64))
+    return fail(FILARK_EINVAL, adjoint ? "adjoint block must be 8 or 16" : "block must be 32 or 64");
   if (waves < 1 || waves > kMaxWaves) return fail(FILARK_EINVAL, "waves must be in [1, %d]", kMaxWaves);
   if (group != 4 && group != 8 && group != 16 && group != 32 && group != 64)
     return fail(FILARK_EINVAL, "group must be 4, 8, 16, 32 or 64 channels");
@@ -326,7 +383,7 @@ extern "C" {
 
 const char *filark_last_error(void) { return g_err.c_str(); }
 
-const char *filark_version(void) { return "filark-mi355x 0.2 (gfx950)"; }
+const char *filark_version(void) { return "filark-mi355x 0.3 (gfx950)"; }
 
 filark_status filark_sos_design(int order, int btype, double f1, double f2, double fs,
                                 double *sos_out, int *n_sec) {
@@ -369,7 +426,9 @@ filark_status filark_sos_init(filark_sos_t *out, const double *sos, int n_sec, i
   hipError_t e = hipMalloc(&st->d_state, bytes);
   if (e == hipSuccess) e = hipMemsetAsync(st->d_state, 0, bytes, stream);
   if (e != hipSuccess) rc = fail(FILARK_EHIP, "state allocation: %s", hipGetErrorString(e));
-  if (rc == FILARK_OK) rc = sos_tables(st, stream);
+  st->adj.tile = default_adj_tile();
+  if (rc == FILARK_OK) rc = sos_tables(st->cas, st->fwd, stream);
+  if (rc == FILARK_OK) rc = sos_tables(st->cas, st->adj, stream);
   if (rc != FILARK_OK) {
     filark_sos_destroy(st);
     return rc;
@@ -401,7 +460,9 @@ filark_status filark_stalta_init(filark_stalta_t *out, double sta_s, double lta_
   if (e == hipSuccess) e = hipMalloc(&st->d_cnt, (size_t)n_ch * sizeof(int64_t));
   if (e == hipSuccess) e = hipMemsetAsync(st->d_cnt, 0, (size_t)n_ch * sizeof(int64_t), stream);
   if (e != hipSuccess) rc = fail(FILARK_EHIP, "state allocation: %s", hipGetErrorString(e));
-  if (rc == FILARK_OK) rc = stalta_tables(st, stream);
+  st->adj.tile = default_adj_tile();
+  if (rc == FILARK_OK) rc = stalta_tables(st->nsta, st->nlta, st->fwd, stream);
+  if (rc == FILARK_OK) rc = stalta_tables(st->nsta, st->nlta, st->adj, stream);
   if (rc != FILARK_OK) {
     filark_stalta_destroy(st);
     return rc;
@@ -510,25 +571,28 @@ filark_status filark_state_set(void *obj, int kind, const void *host_buf, size_t
 
 filark_status filark_tile_set(void *obj, int kind, int block, int waves, int group, hipStream_t stream) {
   if (!obj) return fail(FILARK_EINVAL, "null state");
-  filark_status rc = check_tile(block, waves, group);
+  const bool adjoint = kind == FILARK_TILE_SOS_ADJOINT || kind == FILARK_TILE_STALTA_ADJOINT;
+  filark_status rc = check_tile(block, waves, group, adjoint);
   if (rc != FILARK_OK) return rc;
   Tile t;
   t.block = block;
   t.waves = waves;
   t.group = group;
-  if (kind == FILARK_STATE_SOS) {
+  if (kind == FILARK_STATE_SOS || kind == FILARK_TILE_SOS_ADJOINT) {
     filark_sos_state *st = static_cast<filark_sos_state *>(obj);
-    if (st->tile == t) return FILARK_OK;
+    Tables &tb = adjoint ? st->adj : st->fwd;
+    if (tb.tile == t) return FILARK_OK;
     HIP_TRY(hipStreamSynchronize(stream));
-    st->tile = t;
-    return sos_tables(st, stream);
+    tb.tile = t;
+    return sos_tables(st->cas, tb, stream);
   }
-  if (kind == FILARK_STATE_STALTA) {
+  if (kind == FILARK_STATE_STALTA || kind == FILARK_TILE_STALTA_ADJOINT) {
     filark_stalta_state *st = static_cast<filark_stalta_state *>(obj);
-    if (st->tile == t) return FILARK_OK;
+    Tables &tb = adjoint ? st->adj : st->fwd;
+    if (tb.tile == t) return FILARK_OK;
     HIP_TRY(hipStreamSynchronize(stream));
-    st->tile = t;
-    return stalta_tables(st, stream);
+    tb.tile = t;
+    return stalta_tables(st->nsta, st->nlta, tb, stream);
   }
   return fail(FILARK_EINVAL, "unknown state kind %d", kind);
 }
@@ -536,12 +600,166 @@ filark_status filark_tile_set(void *obj, int kind, int block, int waves, int gro
 filark_status filark_tile_get(const void *obj, int kind, int *block, int *waves, int *group) {
   if (!obj || !block || !waves || !group) return fail(FILARK_EINVAL, "null pointer");
   Tile t;
-  if (kind == FILARK_STATE_SOS) t = static_cast<const filark_sos_state *>(obj)->tile;
-  else if (kind == FILARK_STATE_STALTA) t = static_cast<const filark_stalta_state *>(obj)->tile;
+  if (kind == FILARK_STATE_SOS) t = static_cast<const filark_sos_state *>(obj)->fwd.tile;
+  else if (kind == FILARK_STATE_STALTA) t = static_cast<const filark_stalta_state *>(obj)->fwd.tile;
+  else if (kind == FILARK_TILE_SOS_ADJOINT) t = static_cast<const filark_sos_state *>(obj)->adj.tile;
+  else if (kind == FILARK_TILE_STALTA_ADJOINT) t = static_cast<const filark_stalta_state *>(obj)->adj.tile;
   else return fail(FILARK_EINVAL, "unknown state kind %d", kind);
   *block = t.block;
   *waves = t.waves;
   *group = t.group;
+  return FILARK_OK;
+}
+
+filark_status filark_state_bytes(const void *obj, int kind, size_t *bytes) {
+  if (!obj || !bytes) return fail(FILARK_EINVAL, "null pointer");
+  if (kind == FILARK_STATE_SOS) {
+    const filark_sos_state *st = static_cast<const filark_sos_state *>(obj);
+    *bytes = (size_t)(2 * st->cas.K) * (size_t)st->n_ch * sizeof(double);
+    return FILARK_OK;
+  }
+  if (kind == FILARK_STATE_STALTA) {
+    const filark_stalta_state *st = static_cast<const filark_stalta_state *>(obj);
+    *bytes = (size_t)st->n_ch * (2 * sizeof(double) + sizeof(int64_t));
+    return FILARK_OK;
+  }
+  return fail(FILARK_EINVAL, "unknown state kind %d", kind);
+}
+
+filark_status filark_state_save(const void *obj, int kind, void *dev_dst, hipStream_t stream) {
+  if (!obj || !dev_dst) return fail(FILARK_EINVAL, "null pointer");
+  if (kind == FILARK_STATE_SOS) {
+    const filark_sos_state *st = static_cast<const filark_sos_state *>(obj);
+    HIP_TRY(hipMemcpyAsync(dev_dst, st->d_state, (size_t)(2 * st->cas.K) * st->n_ch * sizeof(double),
+                           hipMemcpyDeviceToDevice, stream));
+    return FILARK_OK;
+  }
+  if (kind == FILARK_STATE_STALTA) {
+    const filark_stalta_state *st = static_cast<const filark_stalta_state *>(obj);
+    char *d = static_cast<char *>(dev_dst);
+    const size_t b1 = 2 * (size_t)st->n_ch * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(d, st->d_state, b1, hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(d + b1, st->d_cnt, (size_t)st->n_ch * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                           stream));
+    return FILARK_OK;
+  }
+  return fail(FILARK_EINVAL, "unknown state kind %d", kind);
+}
+
+filark_status filark_state_load(void *obj, int kind, const void *dev_src, hipStream_t stream) {
+  if (!obj || !dev_src) return fail(FILARK_EINVAL, "null pointer");
+  if (kind == FILARK_STATE_SOS) {
+    filark_sos_state *st = static_cast<filark_sos_state *>(obj);
+    HIP_TRY(hipMemcpyAsync(st->d_state, dev_src, (size_t)(2 * st->cas.K) * st->n_ch * sizeof(double),
+                           hipMemcpyDeviceToDevice, stream));
+    return FILARK_OK;
+  }
+  if (kind == FILARK_STATE_STALTA) {
+    filark_stalta_state *st = static_cast<filark_stalta_state *>(obj);
+    const char *d = static_cast<const char *>(dev_src);
+    const size_t b1 = 2 * (size_t)st->n_ch * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(st->d_state, d, b1, hipMemcpyDeviceToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(st->d_cnt, d + b1, (size_t)st->n_ch * sizeof(int64_t), hipMemcpyDeviceToDevice,
+                           stream));
+    return FILARK_OK;
+  }
+  return fail(FILARK_EINVAL, "unknown state kind %d", kind);
+}
+
+filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, const float *x,
+                                        const float *g, int mode, double scale, float *gx, double *adj,
+                                        double *gsos, int64_t n_ch, int64_t n_t, hipStream_t stream) {
+  if (!sos || !sl) return fail(FILARK_EINVAL, "null state");
+  if (sos->device != sl->device) return fail(FILARK_EINVAL, "states live on different devices");
+  if (sos->n_ch != n_ch || sl->n_ch != n_ch) return fail(FILARK_ESHAPE, "n_ch differs from the states'");
+  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
+  if (mode != FILARK_ADJ_GRAD && mode != FILARK_ADJ_MSE) return fail(FILARK_EINVAL, "unknown mode %d", mode);
+  if (!std::isfinite(scale)) return fail(FILARK_EINVAL, "scale must be finite");
+  if (n_t == 0) return FILARK_OK;
+  if (!x || !g || !gx || !adj || !gsos) return fail(FILARK_EINVAL, "null pointer");
+  if (!(sos->adj.tile == sl->adj.tile))
+    return fail(FILARK_EINVAL, "adjoint tile shapes of the states differ");
+  if (!(sos->fwd.tile == sl->fwd.tile))
+    return fail(FILARK_EINVAL, "tile shapes of the states differ (set both with filark_tile_set)");
+  const Tile ta = sos->adj.tile, tf = sos->fwd.tile;
+  const int K = sos->cas.K;
+  const int64_t rows = launch_rows(ta, n_ch);
+  if (rows == 0 || launch_rows(tf, n_ch) == 0) return fail(FILARK_EINVAL, "n_ch %lld too large", (long long)n_ch);
+  filark_status rc = check_lds(adj_lds_bytes(K, ta.waves, ta.levels()), ta, K, sos->device);
+  if (rc == FILARK_OK) rc = check_lds(fwd_lds_bytes(K, tf.waves, tf.levels()), tf, K, sos->device);
+  if (rc != FILARK_OK) return rc;
+  const int prev_dev = current_device();
+  if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
+
+  // workspace: forward state at every window start (filter [2K][n_ch],
+  // STA/LTA [2][n_ch], counter [n_ch]), per-group coefficient sums
+  const int64_t n_win = (n_t + rows - 1) / rows;
+  const size_t ck_doubles = (size_t)(2 * K + 3) * (size_t)n_ch;  // the counter rides in a double slot
+  const int n_grp = (int)((n_ch + ta.group - 1) / ta.group);
+  rc = grow(&sos->d_ck, &sos->ck_bytes, (size_t)n_win * ck_doubles * sizeof(double), stream);
+  if (rc == FILARK_OK) rc = grow(&sos->d_gpart, &sos->gpart_bytes, (size_t)n_grp * 5 * K * sizeof(double), stream);
+  if (rc != FILARK_OK) {
+    if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
+    return rc;
+  }
+  auto ck_z = [&](int64_t w) { return sos->d_ck + (size_t)w * ck_doubles; };
+  auto ck_s = [&](int64_t w) { return ck_z(w) + (size_t)(2 * K) * n_ch; };
+  auto ck_c = [&](int64_t w) { return reinterpret_cast<int64_t *>(ck_s(w) + 2 * (size_t)n_ch); };
+  hipError_t e = hipMemcpyAsync(ck_z(0), sos->d_state, (size_t)(2 * K) * n_ch * sizeof(double),
+                                hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ck_s(0), sl->d_state, 2 * (size_t)n_ch * sizeof(double), hipMemcpyDeviceToDevice, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ck_c(0), sl->d_cnt, (size_t)n_ch * sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
+  // forward states at the window starts
+  for (int64_t w = 0; w + 1 < n_win && e == hipSuccess; ++w) {
+    e = hipMemcpyAsync(ck_z(w + 1), ck_z(w), ck_doubles * sizeof(double), hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+      e = forward_launches(sos, sl, tf, ck_z(w + 1), ck_s(w + 1), ck_c(w + 1), x + (size_t)(w * rows) * n_ch,
+                           nullptr, nullptr, true, n_ch, rows, stream);
+  }
+  // windows last to first
+  AdjParams p;
+  std::memset(&p, 0, sizeof p);
+  p.g = g;
+  p.n_ch = n_ch;
+  p.cw_log2 = log2_exact(ta.group);
+  p.nw = ta.waves;
+  p.n_grp = n_grp;
+  p.xq = std::max(1, 32 / ta.group);
+  p.n_lev = ta.levels();
+  p.mode = mode;
+  p.scale = scale;
+  p.adj = adj;
+  p.gpart = sos->d_gpart;
+  p.coef = sos->adj.d;
+  p.G = sos->adj.d + sos->adj.off_G;
+  p.Pw = sos->adj.d + sos->adj.off_P;
+  p.dpow = sl->adj.d;
+  p.cs = 1.0 / (double)sl->nsta;
+  p.cl = 1.0 / (double)sl->nlta;
+  p.asd = 1.0 - p.cs;
+  p.ald = 1.0 - p.cl;
+  p.ias = 1.0 / p.asd;
+  p.ial = 1.0 / p.ald;
+  p.nlta = sl->nlta;
+  const uint64_t rowb = (uint64_t)n_ch * 4u;
+  for (int64_t w = n_win - 1; w >= 0 && e == hipSuccess; --w) {
+    const int64_t t0 = w * rows, nt = std::min(rows, n_t - t0);
+    const size_t off = (size_t)t0 * (size_t)n_ch;
+    p.x = x + off;
+    p.g = g + off;
+    p.gx = gx + off;
+    p.n_t = (int32_t)nt;
+    p.range = (int32_t)((uint64_t)nt * rowb);
+    p.zs0 = ck_z(w);
+    p.sl0 = ck_s(w);
+    p.cnt0 = ck_c(w);
+    e = launch_adj(p, K, ta.block, stream);
+  }
+  if (e == hipSuccess) e = launch_adj_reduce(sos->d_gpart, n_grp, 5 * K, gsos, stream);
+  if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
+  if (e != hipSuccess) return fail(FILARK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
   return FILARK_OK;
 }
 
@@ -557,7 +775,10 @@ filark_status filark_check(const void *obj, int kind, hipStream_t stream) {
 filark_status filark_sos_destroy(filark_sos_t st) {
   if (!st) return FILARK_OK;
   if (st->d_state) (void)hipFree(st->d_state);
-  if (st->d_tab) (void)hipFree(st->d_tab);
+  if (st->fwd.d) (void)hipFree(st->fwd.d);
+  if (st->adj.d) (void)hipFree(st->adj.d);
+  if (st->d_ck) (void)hipFree(st->d_ck);
+  if (st->d_gpart) (void)hipFree(st->d_gpart);
   delete st;
   return FILARK_OK;
 }
@@ -566,7 +787,8 @@ filark_status filark_stalta_destroy(filark_stalta_t st) {
   if (!st) return FILARK_OK;
   if (st->d_state) (void)hipFree(st->d_state);
   if (st->d_cnt) (void)hipFree(st->d_cnt);
-  if (st->d_tab) (void)hipFree(st->d_tab);
+  if (st->fwd.d) (void)hipFree(st->fwd.d);
+  if (st->adj.d) (void)hipFree(st->adj.d);
   delete st;
   return FILARK_OK;
 }

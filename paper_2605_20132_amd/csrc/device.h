@@ -1,0 +1,85 @@
+// Device helpers shared by the forward and adjoint kernels (gfx950).
+#pragma once
+
+#include "internal.h"
+
+#define FILARK_CONST __attribute__((address_space(4)))
+
+namespace filark {
+namespace dev {
+
+typedef const FILARK_CONST double cdouble;
+
+__device__ __forceinline__ cdouble *as_const(const double *p) { return (cdouble *)p; }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// A copy of a uniform value that the compiler must treat as new.  Row offsets
+// are formed from it in each phase right where they are used, instead of one
+// set of per-row offsets being kept live in VGPRs across all phases.
+__device__ __forceinline__ uint32_t fresh(uint32_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
+// Kernel parameters are read through the kernarg-segment pointer, taken
+// afresh in every phase: each phase scalar-loads only the fields it uses,
+// and nothing from the parameter block stays live across other phases.
+template <class P>
+__device__ __forceinline__ const FILARK_CONST P *kparams() {
+  const FILARK_CONST P *k = (const FILARK_CONST P *)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(k));
+  return k;
+}
+
+// Raw buffer resource over `range` bytes at `base` (stride 0, byte offsets).
+// Offsets at or past `range` read zero and drop stores; lanes whose channel
+// is past n_ch use an offset of 2^31, which is always out of range.
+constexpr uint32_t kOffInvalid = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, int range) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, range, 0x00020000);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, 0, 0);
+}
+
+// acc += M v for a block-lower-triangular M [NS][NS] (2x2 diagonal blocks)
+// held in LDS; all lanes read the same entries (broadcast).  The fences keep
+// one row of M in registers at a time.
+template <int NS>
+__device__ __forceinline__ void mv_acc(const double *M, const double (&v)[NS], double (&acc)[NS]) {
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    double s = acc[i];
+#pragma unroll
+    for (int j = 0; j < (i / 2 + 1) * 2; ++j) s = fma(M[i * NS + j], v[j], s);
+    acc[i] = s;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// acc += M^T v for the same M (block-upper-triangular product).
+template <int NS>
+__device__ __forceinline__ void mtv_acc(const double *M, const double (&v)[NS], double (&acc)[NS]) {
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    double s = acc[j];
+#pragma unroll
+    for (int i = (j / 2) * 2; i < NS; ++i) s = fma(M[i * NS + j], v[i], s);
+    acc[j] = s;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Channel group of a workgroup: runs of xq consecutive groups share an XCD
+// (workgroups are dealt to the 8 XCDs round-robin by workgroup index).
+__device__ __forceinline__ int group_of(int xq) {
+  const int wg = (int)blockIdx.x, slot = wg >> 3;
+  return uniform((slot / xq) * 8 * xq + (wg & 7) * xq + slot % xq);
+}
+
+}  // namespace dev
+}  // namespace filark

@@ -34,9 +34,7 @@
 // stores are dropped.  Filter arithmetic and all carries are FP64 (v_fma_f64
 // issues at the v_fma_f32 rate here); STA/LTA sums are FP32 within a block
 // with FP64 carries.  No MFMA: the path is HBM-bound.
-#include "internal.h"
-
-#define FILARK_CONST __attribute__((address_space(4)))
+#include "device.h"
 
 namespace filark {
 
@@ -52,58 +50,9 @@ size_t fwd_lds_bytes(int K, int nw, int n_lev) {
 
 namespace {
 
-typedef const FILARK_CONST double cdouble;
-
-__device__ __forceinline__ cdouble *as_const(const double *p) { return (cdouble *)p; }
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-// A copy of a uniform value that the compiler must treat as new.  Row offsets
-// are formed from it in each phase right where they are used, instead of one
-// set of per-row offsets being kept live in VGPRs across all phases.
-__device__ __forceinline__ uint32_t fresh(uint32_t v) {
-  asm volatile("" : "+s"(v));
-  return v;
-}
-
-// Kernel parameters are read through the kernarg-segment pointer, taken
-// afresh in every phase: each phase scalar-loads only the fields it uses,
-// and nothing from the parameter block stays live across other phases.
+using namespace dev;
 typedef const FILARK_CONST FwdParams *kparams_t;
-__device__ __forceinline__ kparams_t kparams() {
-  kparams_t k = (kparams_t)__builtin_amdgcn_kernarg_segment_ptr();
-  asm volatile("" : "+s"(k));
-  return k;
-}
-
-// Raw buffer resource over `range` bytes at `base` (stride 0, byte offsets).
-// Offsets at or past `range` read zero and drop stores; lanes whose channel
-// is past n_ch use an offset of 2^31, which is always out of range.
-constexpr uint32_t kOffInvalid = 0x80000000u;
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, int range) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, range, 0x00020000);
-}
-__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
-}
-__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, 0, 0);
-}
-
-// acc += M v for a block-lower-triangular M [NS][NS] (2x2 diagonal blocks)
-// held in LDS; all lanes read the same entries (broadcast).  The fences keep
-// one row of M in registers at a time.
-template <int NS>
-__device__ __forceinline__ void mv_acc(const double *M, const double (&v)[NS], double (&acc)[NS]) {
-#pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    double s = acc[i];
-#pragma unroll
-    for (int j = 0; j < (i / 2 + 1) * 2; ++j) s = fma(M[i * NS + j], v[j], s);
-    acc[i] = s;
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
+__device__ __forceinline__ kparams_t kparams() { return dev::kparams<FwdParams>(); }
 
 // Pass 1: zero-state block-end projection a = sum_j A^(L-1-j) B x_j.  Row j+1
 // of G is fetched into SGPRs while row j is applied; the fences stop the
@@ -235,11 +184,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fwd_kernel(FwdParams) {
   const int NW = p->nw;
   const int cwl = p->cw_log2;
   const int CW = 1 << cwl, R = kWave >> cwl, NB = NW * R;
-  // Runs of xq consecutive groups share an XCD (workgroups are dealt to the
-  // 8 XCDs round-robin by workgroup index).
-  const int xq = p->xq;
-  const int wg = (int)blockIdx.x, slot = wg >> 3;
-  const int g = uniform((slot / xq) * 8 * xq + (wg & 7) * xq + slot % xq);
+  const int g = group_of(p->xq);
   if (g >= p->n_grp) return;  // whole workgroup, before any barrier
   const int r = lane >> cwl, cl = lane & (CW - 1);
   const int b = w * R + r;                 // block within the window
@@ -323,7 +268,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fwd_kernel(FwdParams) {
     {
       kparams_t q = kparams();
       const __amdgpu_buffer_rsrc_t ry =
-          rsrc(WRITE_Y ? (const void *)q->y : (const void *)q->x, WRITE_Y ? q->range : 0);
+          rsrc(WRITE_Y ? (const void *)q->y : (const void *)q->x, WRITE_Y ? q->out_range : 0);
       pass2<K, L, STALTA, WRITE_Y>(xv, z, ry, vo, fresh(rowb), s_loc, l_loc, jcap, xme, sc, lc);
     }
     if (end_lane) {  // the filter state after the last row, kept by pass 2
@@ -385,7 +330,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fwd_kernel(FwdParams) {
     }
     const int64_t jw = q->nlta - (g0 + row0);
     const int jwarm = jw <= 0 ? 0 : (jw >= L ? L : (int)jw);
-    const __amdgpu_buffer_rsrc_t rc = rsrc(q->cf, q->range);
+    const __amdgpu_buffer_rsrc_t rc = rsrc(q->cf ? (const void *)q->cf : (const void *)q->x, q->out_range);
     passb<L>(xv, (float)Sin, (float)Lin, jwarm, rc, vo, fresh(rowb));
   }
 }

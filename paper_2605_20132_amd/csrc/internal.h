@@ -29,6 +29,7 @@ struct FwdParams {
   int32_t xq;          // consecutive groups placed on one XCD
   int32_t n_lev;       // scan levels (>= 1; level k spans 2^k blocks)
   int32_t range;       // bytes of one [n_t][n_ch] FP32 array (buffer range)
+  int32_t out_range;   // buffer range of y and cf: `range`, or 0 to write neither (states only)
 
   // SOS cascade
   double *zs;          // carried state [2K][n_ch], updated in place
@@ -47,16 +48,51 @@ struct FwdParams {
   float kappa;         // nlta / nsta (cf = kappa * S / L in the scaled sums)
 };
 
+// Parameters of the adjoint kernel: one window of a chunk, processed after
+// the windows that follow it (reverse time).  Same work split as FwdParams.
+// The forward state at the window start is a checkpoint (read only); the
+// adjoint state is read as the adjoint after the window and overwritten with
+// the adjoint before it.
+struct AdjParams {
+  const float *x;      // input [n_t][n_ch]
+  const float *g;      // dL/dcf (mode 0) or the target cf (mode 1) [n_t][n_ch]
+  float *gx;           // dL/dx [n_t][n_ch]
+  int64_t n_ch;
+  int32_t n_t;         // rows in this launch (1 .. NB * L)
+  int32_t cw_log2, nw, n_grp, xq, n_lev, range;
+  int32_t mode;        // 0: g = dL/dcf;  1: g = target, loss = scale * sum (cf - g)^2
+  double scale;
+  const double *zs0;   // forward filter state at the window start [2K][n_ch]
+  const double *sl0;   // forward (sta, lta) at the window start [2][n_ch]
+  const int64_t *cnt0; // global sample index of the window start [n_ch]
+  double *adj;         // adjoint state [2K + 2][n_ch]: (u1, u2) per section, then sta, lta
+  double *gpart;       // [n_grp][5K] coefficient-gradient sums of each group, added to
+  const double *coef, *G, *Pw;  // forward tables (as FwdParams)
+  const double *dpow;           // [n_lev][2] decays^(L 2^k), then [L + 1][2] decays^m
+  double asd, ald;     // 1 - 1/nsta, 1 - 1/nlta
+  double ias, ial;     // 1 / asd, 1 / ald
+  double cs, cl;       // 1/nsta, 1/nlta
+  int64_t nlta;
+};
+
 // Dynamic LDS bytes of a forward workgroup.
 size_t fwd_lds_bytes(int K, int nw, int n_lev);
 
 // Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only.
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, hipStream_t stream);
 
-// Workgroups launched for a parameter set (groups rounded up to whole XCD runs).
-inline int fwd_grid(const FwdParams &p) {
-  const int run = 8 * p.xq;
-  return (p.n_grp + run - 1) / run * run;
+// Workgroups launched for n_grp groups (rounded up to whole XCD runs).
+inline int grid_for(int n_grp, int xq) {
+  const int run = 8 * xq;
+  return (n_grp + run - 1) / run * run;
 }
+inline int fwd_grid(const FwdParams &p) { return grid_for(p.n_grp, p.xq); }
+
+// Adjoint: LDS bytes, launcher (defined in adj.hip; L = 8 or 16, K = 1 .. 8),
+// and the fixed-order sum of the per-group coefficient gradients into
+// gsos[5K] (added to), which also clears gpart.
+size_t adj_lds_bytes(int K, int nw, int n_lev);
+hipError_t launch_adj(const AdjParams &p, int K, int L, hipStream_t stream);
+hipError_t launch_adj_reduce(double *gpart, int n_grp, int n5, double *gsos, hipStream_t stream);
 
 }  // namespace filark
