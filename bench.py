@@ -81,6 +81,104 @@ def cpu_baseline(x_dev, sos, nsta, nlta, chunk, min_seconds=10.0, max_passes=30)
                       f"{el:.1f} s on {cores} host threads"}
 
 
+def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
+    """Forward + adjoint on the differentiation workload: 6000 ch x 30,000
+    samples in 3000-sample chunks, loss = mean (cf - target)^2, target = cf of
+    the same input through the band moved to (1.05 f1, 0.95 f2).  A step is
+    the chunked forward with per-chunk device checkpoints plus the adjoint
+    chain (chunks last to first) giving dL/dx and dL/dtheta."""
+    import synth
+
+    w = synth.make_config5(device=dev)
+    x = w.x
+    n_t, n_ch = x.shape
+    chunk = w.chunk
+    nsta, nlta = round(w.sta_s * w.fs), round(w.lta_s * w.fs)
+    sos = F.sos_design(w.order, w.btype, w.f1, w.f2, w.fs)
+    sos_t = F.sos_design(w.order, w.btype, 1.05 * w.f1, 0.95 * w.f2, w.fs)
+    K = sos.shape[0]
+    splits = [(a, min(n_t, a + chunk)) for a in range(0, n_t, chunk)]
+    tgt = torch.empty_like(x)
+    st_t, sl_t = F.SOSState(sos_t, n_ch), F.StaLtaState(float(nsta), float(nlta), 1.0, n_ch)
+    for a, b in splits:
+        F.sos_stalta_process(st_t, sl_t, x[a:b], cf=tgt[a:b], write_y=False)
+    st, sl = F.SOSState(sos, n_ch), F.StaLtaState(float(nsta), float(nlta), 1.0, n_ch)
+    cks = [(st.save(), sl.save()) for _ in splits]
+    zero_z, zero_s = st.save(), sl.save()
+    cf = torch.empty_like(x)
+    gx = torch.empty_like(x)
+    adj = torch.zeros((2 * K + 2, n_ch), dtype=torch.float64, device=dev)
+    gs = torch.zeros((K, 5), dtype=torch.float64, device=dev)
+    scale = 1.0 / x.numel()
+
+    def step():
+        st.load(zero_z)
+        sl.load(zero_s)
+        for i, (a, b) in enumerate(splits):
+            st.save(cks[i][0])
+            sl.save(cks[i][1])
+            F.sos_stalta_process(st, sl, x[a:b], cf=cf[a:b], write_y=False)
+        adj.zero_()
+        gs.zero_()
+        for i in reversed(range(len(splits))):
+            a, b = splits[i]
+            st.load(cks[i][0])
+            sl.load(cks[i][1])
+            F.sos_stalta_adjoint(st, sl, x[a:b], tgt[a:b], gx[a:b], adj, gs, mode="mse", scale=scale)
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    st.check()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"workload": f"{n_ch} ch x {n_t} samples @ {w.fs:g} Hz in {len(splits)} chunks of {chunk}; "
+                       f"BP order {w.order} ({K} SOS) + STA/LTA {nsta}/{nlta}; loss mean (cf - target)^2; "
+                       "grad wrt x and all coefficients",
+           "ms_per_step": ms, "value": n_ch * n_t / (ms / 1e3), "unit": "channel-samples/s",
+           "algorithmic_gbs": 20.0 * n_ch * n_t / (ms / 1e3) / 1e9}
+    if parity:
+        # the same path on a 64-channel slice against the oracle's reference gradient
+        import numpy as np
+        import oracle
+
+        xs = x[:, :64].contiguous()
+        ts = tgt[:, :64].contiguous()
+        osos = oracle.butter_sos(w.order, w.btype, w.f1, w.f2, w.fs)
+        s2, l2 = F.SOSState(osos, 64), F.StaLtaState(float(nsta), float(nlta), 1.0, 64)
+        ck2 = []
+        for a, b in splits:
+            ck2.append((s2.save(), l2.save()))
+            F.sos_stalta_process(s2, l2, xs[a:b], write_y=False)
+        g2 = torch.empty_like(xs)
+        a2 = torch.zeros((2 * K + 2, 64), dtype=torch.float64, device=dev)
+        gs2 = torch.zeros((K, 5), dtype=torch.float64, device=dev)
+        sc2 = 1.0 / xs.numel()
+        for i in reversed(range(len(splits))):
+            a, b = splits[i]
+            s2.load(ck2[i][0])
+            l2.load(ck2[i][1])
+            F.sos_stalta_adjoint(s2, l2, xs[a:b], ts[a:b], g2[a:b], a2, gs2, mode="mse", scale=sc2)
+        torch.cuda.synchronize()
+        _, ogx, ogs, _ = oracle.stalta_grad(osos, xs.double().cpu().numpy(), ts.double().cpu().numpy(), nsta,
+                                            nlta, sc2)
+        gxh = g2.double().cpu().numpy()
+        num = np.linalg.norm(gxh - ogx, axis=0)
+        den = np.linalg.norm(ogx, axis=0)
+        res["parity"] = {"channels": 64,
+                         "max_rel_rms_gx": float(np.max(num / np.where(den > 0, den, 1.0))),
+                         "rel_l2_gtheta": float(np.linalg.norm(gs2.cpu().numpy() - ogs) / np.linalg.norm(ogs)),
+                         "tolerance": 1e-5}
+    log(f"[bench] fwd+adjoint {ms:.2f} ms/step -> {res['value']:.3e} ch-samples/s"
+        + (f"; parity gx {res['parity']['max_rel_rms_gx']:.2e} gtheta {res['parity']['rel_l2_gtheta']:.2e}"
+           if parity else ""))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,8 +186,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--n-ch", type=int, default=6000)
     ap.add_argument("--n-t", type=int, default=90_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain device copy of 512 MiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -215,6 +316,23 @@ def main():
     except Exception as e:  # capture is an optional extra measurement
         log(f"[bench] graph capture unavailable: {e}")
 
+    if args.calib_copy:
+        src = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        flush = torch.empty(256 << 20, dtype=torch.float32, device=dev)
+        flush.fill_(2.0)  # 1 GiB written after src: src is not cache resident when copied
+        del flush
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
+        del src, dst
+
+    fwd_adj = None
+    if not args.no_adjoint:
+        fwd_adj = fwd_adjoint_leg(F, torch, dev, 3, not args.no_parity)
+
     t = measured_traffic()
     traffic = None
     if t is not None:
@@ -243,6 +361,7 @@ def main():
                                "y and cf written",
                    "io": "fp32", "filter_arith": "fp64", "stalta_arith": "fp32 block / fp64 carry"},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "graph_replay": graph,
+        "fwd_adjoint": fwd_adj,
     }
     print(json.dumps(out))
 

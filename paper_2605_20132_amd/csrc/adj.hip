@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
   const int NW = p->nw;
   const int cwl = p->cw_log2;
   const int CW = 1 << cwl, R = kWave >> cwl, NB = NW * R;
-  const int g = group_of(p->xq);
+  const int g = group_of(p->per_xcd);
   if (g >= p->n_grp) return;  // whole workgroup, before any barrier
   const int r = lane >> cwl, cl = lane & (CW - 1);
   const int b = w * R + r;
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
 template <int K, int L>
 hipError_t launch_one(const AdjParams &p, hipStream_t stream) {
   const size_t lds = adj_lds_bytes(K, p.nw, p.n_lev);
-  hipLaunchKernelGGL((adj_kernel<K, L>), dim3((unsigned)grid_for(p.n_grp, p.xq)),
+  hipLaunchKernelGGL((adj_kernel<K, L>), dim3((unsigned)grid_for(p.per_xcd)),
                      dim3((unsigned)(p.nw * kWave)), lds, stream, p);
   return hipGetLastError();
 }

@@ -183,11 +183,11 @@ struct filark_stalta_state {
 
 namespace {
 
-// Default adjoint tile: 8-sample blocks, 8 waves, groups of 8 channels
-// (windows of 512 rows).
+// Default adjoint tile: 16-sample blocks, 8 waves, groups of 8 channels
+// (windows of 1024 rows).
 Tile default_adj_tile() {
   Tile t;
-  t.block = 8;
+  t.block = 16;
   t.waves = 8;
   t.group = 8;
   return t;
@@ -285,7 +285,7 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
   p.cw_log2 = log2_exact(t.group);
   p.nw = t.waves;
   p.n_grp = (int)((n_ch + t.group - 1) / t.group);
-  p.xq = std::max(1, 32 / t.group);  // groups sharing one 128-byte line
+  p.per_xcd = per_xcd_for(p.n_grp);
   p.n_lev = t.levels();
   if (sos) {
     p.zs = zs;
@@ -726,7 +726,7 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
   p.cw_log2 = log2_exact(ta.group);
   p.nw = ta.waves;
   p.n_grp = n_grp;
-  p.xq = std::max(1, 32 / ta.group);
+  p.per_xcd = per_xcd_for(n_grp);
   p.n_lev = ta.levels();
   p.mode = mode;
   p.scale = scale;

@@ -74,11 +74,13 @@ __device__ __forceinline__ void mtv_acc(const double *M, const double (&v)[NS], 
   }
 }
 
-// Channel group of a workgroup: runs of xq consecutive groups share an XCD
-// (workgroups are dealt to the 8 XCDs round-robin by workgroup index).
-__device__ __forceinline__ int group_of(int xq) {
-  const int wg = (int)blockIdx.x, slot = wg >> 3;
-  return uniform((slot / xq) * 8 * xq + (wg & 7) * xq + slot % xq);
+// Channel group of a workgroup.  Workgroups are dealt to the 8 XCDs
+// round-robin by index, so workgroup w runs on XCD w % 8; XCD x is given the
+// contiguous slab of groups [x * per_xcd, (x + 1) * per_xcd), which keeps the
+// rows of neighbouring groups, which share cache lines, in one L2.
+__device__ __forceinline__ int group_of(int per_xcd) {
+  const int wg = (int)blockIdx.x;
+  return uniform((wg & 7) * per_xcd + (wg >> 3));
 }
 
 }  // namespace dev

@@ -28,8 +28,9 @@
 // the whole chunk; lane (r, cl) of wave w takes channel cl and block
 // b = w * (64/cw) + r, so the carries never leave the workgroup: no
 // inter-workgroup waits, and the result does not depend on timing.  A wave
-// load of one row index touches 64/cw runs of cw * 4 contiguous bytes; groups
-// that share a 128-byte line are placed on one XCD so its L2 merges them.
+// load of one row index touches 64/cw runs of cw * 4 contiguous bytes; every
+// XCD takes a contiguous slab of channel groups, so the groups that share
+// cache lines (and DRAM pages) meet in one L2.
 // Rows past the chunk end fall outside the buffer range: loads return zero,
 // stores are dropped.  Filter arithmetic and all carries are FP64 (v_fma_f64
 // issues at the v_fma_f32 rate here); STA/LTA sums are FP32 within a block
@@ -175,7 +176,8 @@ __device__ __forceinline__ void passb(const float (&xv)[L], float Sf, float Lf, 
 }
 
 template <int K, int L, bool STALTA, bool WRITE_Y>
-__global__ void __launch_bounds__(kMaxWaves * kWave) fwd_kernel(FwdParams) {
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L == 64 ? 3 : 1)))
+fwd_kernel(FwdParams) {
   constexpr int NS = 2 * K;
   extern __shared__ double lds[];
   kparams_t p = kparams();
@@ -184,7 +186,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fwd_kernel(FwdParams) {
   const int NW = p->nw;
   const int cwl = p->cw_log2;
   const int CW = 1 << cwl, R = kWave >> cwl, NB = NW * R;
-  const int g = group_of(p->xq);
+  const int g = group_of(p->per_xcd);
   if (g >= p->n_grp) return;  // whole workgroup, before any barrier
   const int r = lane >> cwl, cl = lane & (CW - 1);
   const int b = w * R + r;                 // block within the window

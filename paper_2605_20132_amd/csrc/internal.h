@@ -26,7 +26,7 @@ struct FwdParams {
   int32_t cw_log2;     // log2 of channels per group
   int32_t nw;          // waves per workgroup
   int32_t n_grp;       // channel groups
-  int32_t xq;          // consecutive groups placed on one XCD
+  int32_t per_xcd;     // channel groups per XCD slab (ceil(n_grp / 8))
   int32_t n_lev;       // scan levels (>= 1; level k spans 2^k blocks)
   int32_t range;       // bytes of one [n_t][n_ch] FP32 array (buffer range)
   int32_t out_range;   // buffer range of y and cf: `range`, or 0 to write neither (states only)
@@ -59,7 +59,7 @@ struct AdjParams {
   float *gx;           // dL/dx [n_t][n_ch]
   int64_t n_ch;
   int32_t n_t;         // rows in this launch (1 .. NB * L)
-  int32_t cw_log2, nw, n_grp, xq, n_lev, range;
+  int32_t cw_log2, nw, n_grp, per_xcd, n_lev, range;
   int32_t mode;        // 0: g = dL/dcf;  1: g = target, loss = scale * sum (cf - g)^2
   double scale;
   const double *zs0;   // forward filter state at the window start [2K][n_ch]
@@ -81,12 +81,10 @@ size_t fwd_lds_bytes(int K, int nw, int n_lev);
 // Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only.
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, hipStream_t stream);
 
-// Workgroups launched for n_grp groups (rounded up to whole XCD runs).
-inline int grid_for(int n_grp, int xq) {
-  const int run = 8 * xq;
-  return (n_grp + run - 1) / run * run;
-}
-inline int fwd_grid(const FwdParams &p) { return grid_for(p.n_grp, p.xq); }
+// Channel groups per XCD slab and workgroups launched for n_grp groups.
+inline int per_xcd_for(int n_grp) { return (n_grp + 7) / 8; }
+inline int grid_for(int per_xcd) { return 8 * per_xcd; }
+inline int fwd_grid(const FwdParams &p) { return grid_for(p.per_xcd); }
 
 // Adjoint: LDS bytes, launcher (defined in adj.hip; L = 8 or 16, K = 1 .. 8),
 // and the fixed-order sum of the per-group coefficient gradients into
