@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "channel-samples/s and % HBM peak, plain fwd vs batched vs fwd+adjoint at ≤1e-5 rel err"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2605_20132_amd", "csrc", "fwd.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2605_20132_amd", "csrc", f) for f in ("fwd.hip", "device.h", "internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel_6000ch_traffic.json")
 
 
@@ -38,8 +38,11 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
