@@ -75,6 +75,7 @@ enum { FILARK_ADJ_GRAD = 0, FILARK_ADJ_MSE = 1 };
 
 typedef struct filark_sos_state *filark_sos_t;
 typedef struct filark_stalta_state *filark_stalta_t;
+typedef struct filark_batch *filark_batch_t;
 
 /*
  * Butterworth design by the bilinear transform with pre-warped band edges
@@ -222,6 +223,36 @@ filark_status filark_state_load(void *st, int kind, const void *dev_src, hipStre
 filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, const float *x,
                                         const float *g, int mode, double scale, float *gx, double *adj,
                                         double *gsos, int64_t n_ch, int64_t n_t, hipStream_t stream);
+
+/*
+ * Batched filtering of many independent streams in one launch sequence (the
+ * stateful SOS operator of Section 3.4 applied to several records at once;
+ * streams may differ in channel count, chunk length and filter).
+ *   _create  takes n SOS state objects (one per stream; each keeps its own
+ *            state and tables).  All must share the tile's block and waves;
+ *            the channel group may differ per stream (per-stream tuning).
+ *   _bind    records one chunk per stream: in[s], out[s] device FP32
+ *            [n_t[s]][n_ch of state s] (host arrays of device pointers;
+ *            n_t[s] = 0 skips the stream), builds the work tables and uploads
+ *            them (synchronous).  Rebind when pointers or lengths change.
+ *   _launch  enqueues the bound work on `stream`: a fill kernel that clears
+ *            the completion stamps, then one kernel per (window round,
+ *            section count), each covering every stream of that kind.  It
+ *            allocates nothing and does not synchronise, so it may be
+ *            captured in a HIP graph; every launch or replay advances each
+ *            stream's state by its chunk, exactly like filark_sos_process.
+ *   _stamps  synchronises `stream` and copies n + 1 uint64 values: the
+ *            completion time of each stream's last workgroup and, last, the
+ *            time the launch started, in ticks of the device's 100 MHz clock.
+ * SOS only (no STA/LTA).  Errors as elsewhere; FILARK_EINVAL if a stream's
+ * tile does not fit the device or the state objects disagree.
+ */
+filark_status filark_batch_create(filark_batch_t *b, int n, const filark_sos_t *states, hipStream_t stream);
+filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float *const *out,
+                                const int64_t *n_t, hipStream_t stream);
+filark_status filark_batch_launch(filark_batch_t b, hipStream_t stream);
+filark_status filark_batch_stamps(filark_batch_t b, uint64_t *host, hipStream_t stream);
+filark_status filark_batch_destroy(filark_batch_t b);
 
 /*
  * Synchronise `stream` and report an asynchronous HIP error of the work

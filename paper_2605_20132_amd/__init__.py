@@ -32,7 +32,8 @@ EXPORTS = (
     "filark_stalta_process", "filark_sos_stalta_process", "filark_state_get", "filark_state_set",
     "filark_check", "filark_sos_destroy", "filark_stalta_destroy", "filark_last_error",
     "filark_version", "filark_tile_set", "filark_tile_get", "filark_state_bytes", "filark_state_save",
-    "filark_state_load", "filark_sos_stalta_adjoint",
+    "filark_state_load", "filark_sos_stalta_adjoint", "filark_batch_create", "filark_batch_bind",
+    "filark_batch_launch", "filark_batch_stamps", "filark_batch_destroy",
 )
 
 
@@ -74,6 +75,11 @@ def lib():
     L.filark_state_load.argtypes = [vp, ctypes.c_int, vp, vp]
     L.filark_sos_stalta_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp, i64,
                                             i64, vp]
+    L.filark_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), vp]
+    L.filark_batch_bind.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64), vp]
+    L.filark_batch_launch.argtypes = [vp, vp]
+    L.filark_batch_stamps.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), vp]
+    L.filark_batch_destroy.argtypes = [vp]
     L.filark_sos_destroy.argtypes = [vp]
     L.filark_stalta_destroy.argtypes = [vp]
     for name in EXPORTS:
@@ -343,3 +349,54 @@ def sos_stalta_adjoint(sos: SOSState, sl: StaLtaState, x, g, gx=None, adj=None, 
                                            float(scale), _dev_f32(gx, "gx"), ctypes.c_void_p(adj.data_ptr()),
                                            ctypes.c_void_p(gsos.data_ptr()), n_ch, n_t, _stream(stream)))
     return gx, adj, gsos
+
+
+class Batch:
+    """Many independent SOS streams filtered by one launch sequence (see
+    filark_batch_* in include/filark.h).  Each stream keeps its SOSState;
+    all states must share the tile's block and waves, the group may differ."""
+
+    def __init__(self, states, stream=None):
+        self.states = list(states)
+        arr = (ctypes.c_void_p * len(self.states))(*[st.handle.value for st in self.states])
+        self._h = ctypes.c_void_p()
+        _check(lib().filark_batch_create(ctypes.byref(self._h), len(self.states), arr, _stream(stream)))
+        self._bound = None
+
+    def bind(self, xs, ys, stream=None):
+        """One chunk per stream: xs[s], ys[s] float32 CUDA tensors [n_t_s, n_ch_s]."""
+        n = len(self.states)
+        if len(xs) != n or len(ys) != n:
+            raise FilarkError(EINVAL, "need one input and one output per stream")
+        ins = (ctypes.c_void_p * n)()
+        outs = (ctypes.c_void_p * n)()
+        nts = (ctypes.c_int64 * n)()
+        for i, (x, y, st) in enumerate(zip(xs, ys, self.states)):
+            if x.shape[1] != st.n_ch or y.shape != x.shape:
+                raise FilarkError(ESHAPE, f"stream {i}: shapes do not match its state")
+            ins[i] = _dev_f32(x, "x").value
+            outs[i] = _dev_f32(y, "y").value
+            nts[i] = x.shape[0]
+        _check(lib().filark_batch_bind(self._h, ins, outs, nts, _stream(stream)))
+        self._bound = (list(xs), list(ys))  # keep the buffers alive while bound
+
+    def launch(self, stream=None):
+        _check(lib().filark_batch_launch(self._h, _stream(stream)))
+
+    def stamps(self, stream=None) -> np.ndarray:
+        """Per-stream completion ticks and, last, the start tick (100 MHz)."""
+        out = np.zeros(len(self.states) + 1, dtype=np.uint64)
+        _check(lib().filark_batch_stamps(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                         _stream(stream)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().filark_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -181,6 +181,23 @@ struct filark_stalta_state {
   Tables adj;
 };
 
+struct filark_batch {
+  int device = 0;
+  std::vector<filark_sos_state *> st;
+  int L = 0, nw = 0;
+  FwdParams *d_descs = nullptr;
+  size_t descs_bytes = 0;
+  BatchItem *d_items = nullptr;
+  size_t items_bytes = 0;
+  unsigned long long *d_stamps = nullptr;
+  struct Node {
+    int K, n_items, max_lev;
+    size_t item_off;
+  };
+  std::vector<Node> nodes;
+  bool bound = false;
+};
+
 namespace {
 
 // Default adjoint tile: 16-sample blocks, 8 waves, groups of 8 channels
@@ -365,6 +382,17 @@ filark_status grow(double **buf, size_t *have, size_t need, hipStream_t stream) 
   HIP_TRY(hipMalloc(buf, need));
   HIP_TRY(hipMemsetAsync(*buf, 0, need, stream));
   *have = need;
+  return FILARK_OK;
+}
+
+template <class T>
+filark_status grow_raw(T **buf, size_t *have, size_t need) {
+  if (*buf && *have >= need) return FILARK_OK;
+  if (*buf) (void)hipFree(*buf);
+  *buf = nullptr;
+  *have = 0;
+  HIP_TRY(hipMalloc(reinterpret_cast<void **>(buf), std::max<size_t>(need, 256)));
+  *have = std::max<size_t>(need, 256);
   return FILARK_OK;
 }
 
@@ -760,6 +788,158 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
   if (e == hipSuccess) e = launch_adj_reduce(sos->d_gpart, n_grp, 5 * K, gsos, stream);
   if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status filark_batch_create(filark_batch_t *out, int n, const filark_sos_t *states, hipStream_t stream) {
+  if (!out) return fail(FILARK_EINVAL, "null batch pointer");
+  *out = nullptr;
+  if (n < 1 || n > 4096 || !states) return fail(FILARK_EINVAL, "need 1 .. 4096 states");
+  for (int i = 0; i < n; ++i)
+    if (!states[i]) return fail(FILARK_EINVAL, "null state %d", i);
+  const Tile t0 = states[0]->fwd.tile;
+  for (int i = 0; i < n; ++i) {
+    if (states[i]->device != states[0]->device) return fail(FILARK_EINVAL, "states live on different devices");
+    if (states[i]->fwd.tile.block != t0.block || states[i]->fwd.tile.waves != t0.waves)
+      return fail(FILARK_EINVAL, "state %d: block and waves must match state 0's (group may differ)", i);
+    for (int j = 0; j < i; ++j)
+      if (states[j] == states[i]) return fail(FILARK_EINVAL, "state %d appears twice", i);
+  }
+  filark_batch *b = new (std::nothrow) filark_batch();
+  if (!b) return fail(FILARK_ENOMEM, "host allocation failed");
+  b->device = states[0]->device;
+  b->st.assign(states, states + n);
+  b->L = t0.block;
+  b->nw = t0.waves;
+  hipError_t e = hipMalloc(&b->d_stamps, (size_t)(n + 1) * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_stamps, 0, (size_t)(n + 1) * sizeof(unsigned long long), stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    filark_batch_destroy(b);
+    return fail(FILARK_EHIP, "batch allocation: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return FILARK_OK;
+}
+
+filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float *const *out, const int64_t *n_t,
+                                hipStream_t stream) {
+  if (!b || !in || !out || !n_t) return fail(FILARK_EINVAL, "null pointer");
+  const int n = (int)b->st.size();
+  std::vector<FwdParams> descs;
+  struct Win {
+    int s, K, desc, n_grp, n_lev;
+  };
+  std::vector<std::vector<Win>> rounds;
+  for (int s = 0; s < n; ++s) {
+    filark_sos_state *st = b->st[s];
+    const Tile &t = st->fwd.tile;
+    if (n_t[s] < 0) return fail(FILARK_EINVAL, "stream %d: negative n_t", s);
+    if (n_t[s] > 0 && (!in[s] || !out[s])) return fail(FILARK_EINVAL, "stream %d: null pointer", s);
+    const int64_t rows = launch_rows(t, st->n_ch);
+    if (rows == 0) return fail(FILARK_EINVAL, "stream %d: n_ch too large for its tile", s);
+    const int K = st->cas.K;
+    filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels()), t, K, b->device);
+    if (rc != FILARK_OK) return rc;
+    const uint64_t rowb = (uint64_t)st->n_ch * 4u;
+    for (int64_t t0 = 0, r = 0; t0 < n_t[s]; t0 += rows, ++r) {
+      const int64_t nt = std::min(rows, n_t[s] - t0);
+      FwdParams p;
+      std::memset(&p, 0, sizeof p);
+      const size_t off = (size_t)t0 * (size_t)st->n_ch;
+      p.x = in[s] + off;
+      p.y = out[s] + off;
+      p.n_ch = st->n_ch;
+      p.n_t = (int32_t)nt;
+      p.cw_log2 = log2_exact(t.group);
+      p.nw = t.waves;
+      p.n_grp = (int)((st->n_ch + t.group - 1) / t.group);
+      p.per_xcd = per_xcd_for(p.n_grp);
+      p.n_lev = t.levels();
+      p.range = (int32_t)((uint64_t)nt * rowb);
+      p.out_range = p.range;
+      p.zs = st->d_state;
+      p.coef = st->fwd.d;
+      p.G = st->fwd.d + st->fwd.off_G;
+      p.Pw = st->fwd.d + st->fwd.off_P;
+      if ((int64_t)rounds.size() <= r) rounds.resize(r + 1);
+      rounds[r].push_back({s, K, (int)descs.size(), p.n_grp, p.n_lev});
+      descs.push_back(p);
+    }
+  }
+  // items: per round and filter length, every XCD gets a contiguous slab of
+  // each stream's groups; workgroup i runs on XCD i % 8
+  std::vector<BatchItem> items;
+  b->nodes.clear();
+  for (const auto &wins : rounds) {
+    for (int K = 1; K <= kMaxSections; ++K) {
+      std::vector<BatchItem> lists[8];
+      int max_lev = 0;
+      for (const Win &w : wins) {
+        if (w.K != K) continue;
+        max_lev = std::max(max_lev, w.n_lev);
+        const int per = per_xcd_for(w.n_grp);
+        for (int x = 0; x < 8; ++x)
+          for (int g = x * per; g < std::min(w.n_grp, (x + 1) * per); ++g) lists[x].push_back({w.desc, g, w.s, 0});
+      }
+      size_t len = 0;
+      for (auto &l : lists) len = std::max(len, l.size());
+      if (len == 0) continue;
+      const size_t off = items.size();
+      for (size_t i = 0; i < len; ++i)
+        for (int x = 0; x < 8; ++x) items.push_back(i < lists[x].size() ? lists[x][i] : BatchItem{-1, 0, 0, 0});
+      b->nodes.push_back({K, (int)(items.size() - off), max_lev, off});
+    }
+  }
+  const int prev_dev = current_device();
+  if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
+  HIP_TRY(hipStreamSynchronize(stream));
+  filark_status rc = grow_raw(&b->d_descs, &b->descs_bytes, std::max<size_t>(1, descs.size()) * sizeof(FwdParams));
+  if (rc == FILARK_OK) rc = grow_raw(&b->d_items, &b->items_bytes, std::max<size_t>(1, items.size()) * sizeof(BatchItem));
+  hipError_t e = hipSuccess;
+  if (rc == FILARK_OK && !descs.empty())
+    e = hipMemcpy(b->d_descs, descs.data(), descs.size() * sizeof(FwdParams), hipMemcpyHostToDevice);
+  if (rc == FILARK_OK && e == hipSuccess && !items.empty())
+    e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+  if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
+  if (rc != FILARK_OK) return rc;
+  if (e != hipSuccess) return fail(FILARK_EHIP, "batch upload: %s", hipGetErrorString(e));
+  b->bound = true;
+  return FILARK_OK;
+}
+
+filark_status filark_batch_launch(filark_batch_t b, hipStream_t stream) {
+  if (!b) return fail(FILARK_EINVAL, "null batch");
+  if (!b->bound) return fail(FILARK_EINVAL, "batch not bound (filark_batch_bind)");
+  const int prev_dev = current_device();
+  if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
+  hipError_t e = launch_stamp_reset(b->d_stamps, (int)b->st.size(), stream);
+  for (const auto &nd : b->nodes) {
+    if (e != hipSuccess) break;
+    BatchParams bp;
+    bp.descs = b->d_descs;
+    bp.items = b->d_items + nd.item_off;
+    bp.stamps = b->d_stamps;
+    e = launch_fwd_batch(bp, nd.K, b->L, nd.n_items, b->nw, nd.max_lev, stream);
+  }
+  if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
+  if (e != hipSuccess) return fail(FILARK_EHIP, "batch launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status filark_batch_stamps(filark_batch_t b, uint64_t *host, hipStream_t stream) {
+  if (!b || !host) return fail(FILARK_EINVAL, "null pointer");
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipMemcpy(host, b->d_stamps, (b->st.size() + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  return FILARK_OK;
+}
+
+filark_status filark_batch_destroy(filark_batch_t b) {
+  if (!b) return FILARK_OK;
+  if (b->d_descs) (void)hipFree(b->d_descs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_stamps) (void)hipFree(b->d_stamps);
+  delete b;
   return FILARK_OK;
 }
 

@@ -53,15 +53,27 @@ namespace {
 
 using namespace dev;
 typedef const FILARK_CONST FwdParams *kparams_t;
-__device__ __forceinline__ kparams_t kparams() { return dev::kparams<FwdParams>(); }
+
+// Where a workgroup's parameter block lives: the kernarg segment (one stream
+// per launch) or a descriptor in device memory (batched launches).  get()
+// hands out a copy the compiler must treat as new, so each phase scalar-loads
+// only the fields it uses.
+struct PSrc {
+  kparams_t base;
+  __device__ __forceinline__ kparams_t get() const {
+    kparams_t k = base;
+    asm volatile("" : "+s"(k));
+    return k;
+  }
+};
 
 // Pass 1: zero-state block-end projection a = sum_j A^(L-1-j) B x_j.  Row j+1
 // of G is fetched into SGPRs while row j is applied; the fences stop the
 // scheduler from hoisting the whole table into SGPRs.
 template <int K, int L>
-__device__ __forceinline__ void pass1(const float (&xv)[L], double (&a)[2 * K]) {
+__device__ __forceinline__ void pass1(PSrc ps, const float (&xv)[L], double (&a)[2 * K]) {
   constexpr int NS = 2 * K;
-  cdouble *G = as_const(kparams()->G);
+  cdouble *G = as_const(ps.get()->G);
   double gn[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
@@ -91,10 +103,10 @@ __device__ __forceinline__ void pass1(const float (&xv)[L], double (&a)[2 * K]) 
 // `keep` and the sums so far are kept: in the block that holds the last row
 // of the launch, that is the carried state.
 template <int K, int L, bool STALTA, bool WRITE_Y>
-__device__ __forceinline__ void pass2(float (&xv)[L], double (&z)[2 * K], __amdgpu_buffer_rsrc_t ry,
+__device__ __forceinline__ void pass2(PSrc ps, float (&xv)[L], double (&z)[2 * K], __amdgpu_buffer_rsrc_t ry,
                                       uint32_t vo, uint32_t rowb, double &s_loc, double &l_loc,
                                       int jcap, double *keep, double &sc, double &lc) {
-  kparams_t p = kparams();
+  kparams_t p = ps.get();
   cdouble *coef = as_const(p->coef);
   const double asd = p->asd, ald = p->ald;
   double cb0[K], cb1[K], cb2[K], cna1[K], cna2[K];
@@ -137,9 +149,9 @@ __device__ __forceinline__ void pass2(float (&xv)[L], double (&z)[2 * K], __amdg
 
 // STA/LTA sums of a block of an already filtered input, from zero.
 template <int L>
-__device__ __forceinline__ void sums(const float (&xv)[L], double &s_loc, double &l_loc, int jcap,
+__device__ __forceinline__ void sums(PSrc ps, const float (&xv)[L], double &s_loc, double &l_loc, int jcap,
                                      double &sc, double &lc) {
-  kparams_t p = kparams();
+  kparams_t p = ps.get();
   const double asd = p->asd, ald = p->ald;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
@@ -159,9 +171,9 @@ __device__ __forceinline__ void sums(const float (&xv)[L], double &s_loc, double
 // characteristic function, stored as produced.  Rows before the warm-up
 // boundary (block row < jwarm) give zero.
 template <int L>
-__device__ __forceinline__ void passb(const float (&xv)[L], float Sf, float Lf, int jwarm,
+__device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, float Lf, int jwarm,
                                       __amdgpu_buffer_rsrc_t rc, uint32_t vo, uint32_t rowb) {
-  kparams_t p = kparams();
+  kparams_t p = ps.get();
   const float as = p->as, al = p->al, kappa = p->kappa;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
@@ -175,19 +187,18 @@ __device__ __forceinline__ void passb(const float (&xv)[L], float Sf, float Lf, 
   }
 }
 
+// One workgroup's work: channel group g of the stream described by ps, over
+// one window of rows.
 template <int K, int L, bool STALTA, bool WRITE_Y>
-__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L == 64 ? 3 : 1)))
-fwd_kernel(FwdParams) {
+__device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   constexpr int NS = 2 * K;
   extern __shared__ double lds[];
-  kparams_t p = kparams();
+  kparams_t p = ps.get();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x / kWave);
   const int NW = p->nw;
   const int cwl = p->cw_log2;
   const int CW = 1 << cwl, R = kWave >> cwl, NB = NW * R;
-  const int g = group_of(p->per_xcd);
-  if (g >= p->n_grp) return;  // whole workgroup, before any barrier
   const int r = lane >> cwl, cl = lane & (CW - 1);
   const int b = w * R + r;                 // block within the window
   const int my = w * kWave + lane;         // = b * CW + cl, the lane's LDS row
@@ -222,7 +233,7 @@ fwd_kernel(FwdParams) {
 
   float xv[L];
   {
-    const __amdgpu_buffer_rsrc_t rx = rsrc(kparams()->x, kparams()->range);
+    const __amdgpu_buffer_rsrc_t rx = rsrc(ps.get()->x, ps.get()->range);
     const uint32_t rb = fresh(rowb);
 #pragma unroll
     for (int j = 0; j < L; ++j) {
@@ -235,7 +246,7 @@ fwd_kernel(FwdParams) {
 
   if constexpr (K > 0) {
     double a[NS];
-    pass1<K, L>(xv, a);
+    pass1<K, L>(ps, xv, a);
     if (b == 0) {  // fold in the carried state: a += P z0
       double z0[NS];
 #pragma unroll
@@ -268,25 +279,25 @@ fwd_kernel(FwdParams) {
     }
     __syncthreads();  // the capture below reuses the exchange
     {
-      kparams_t q = kparams();
+      kparams_t q = ps.get();
       const __amdgpu_buffer_rsrc_t ry =
           rsrc(WRITE_Y ? (const void *)q->y : (const void *)q->x, WRITE_Y ? q->out_range : 0);
-      pass2<K, L, STALTA, WRITE_Y>(xv, z, ry, vo, fresh(rowb), s_loc, l_loc, jcap, xme, sc, lc);
+      pass2<K, L, STALTA, WRITE_Y>(ps, xv, z, ry, vo, fresh(rowb), s_loc, l_loc, jcap, xme, sc, lc);
     }
     if (end_lane) {  // the filter state after the last row, kept by pass 2
-      double *zs = kparams()->zs;
+      double *zs = ps.get()->zs;
 #pragma unroll
       for (int i = 0; i < NS; ++i) zs[i * n_ch + c] = xme[i];
     }
   } else {
-    sums<L>(xv, s_loc, l_loc, jcap, sc, lc);
+    sums<L>(ps, xv, s_loc, l_loc, jcap, sc, lc);
   }
 
   if constexpr (STALTA) {
     int64_t g0 = 0;
     double S0 = 0.0, L0 = 0.0;
     if (cval) {
-      kparams_t q = kparams();
+      kparams_t q = ps.get();
       g0 = q->cnt[c];
       if (b == 0) {
         S0 = q->sl[c] * q->nsta_d;
@@ -294,7 +305,7 @@ fwd_kernel(FwdParams) {
       }
     }
     {
-      cdouble *dp = as_const(kparams()->dpow);
+      cdouble *dp = as_const(ps.get()->dpow);
       if (b == 0) {
         s_loc = fma(dp[0], S0, s_loc);
         l_loc = fma(dp[1], L0, l_loc);
@@ -320,7 +331,7 @@ fwd_kernel(FwdParams) {
       Sin = xsl[2 * (my - CW)];
       Lin = xsl[2 * (my - CW) + 1];
     }
-    kparams_t q = kparams();
+    kparams_t q = ps.get();
     if (end_lane) {
       // sums after the last row, from the block entry and the partial block
       // sums kept at that row
@@ -333,7 +344,66 @@ fwd_kernel(FwdParams) {
     const int64_t jw = q->nlta - (g0 + row0);
     const int jwarm = jw <= 0 ? 0 : (jw >= L ? L : (int)jw);
     const __amdgpu_buffer_rsrc_t rc = rsrc(q->cf ? (const void *)q->cf : (const void *)q->x, q->out_range);
-    passb<L>(xv, (float)Sin, (float)Lin, jwarm, rc, vo, fresh(rowb));
+    passb<L>(ps, xv, (float)Sin, (float)Lin, jwarm, rc, vo, fresh(rowb));
+  }
+}
+
+template <int K, int L, bool STALTA, bool WRITE_Y>
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L == 64 ? 3 : 1)))
+fwd_kernel(FwdParams) {
+  const PSrc ps{dev::kparams<FwdParams>()};
+  const int g = group_of(ps.get()->per_xcd);
+  if (g >= ps.get()->n_grp) return;  // whole workgroup, before any barrier
+  fwd_body<K, L, STALTA, WRITE_Y>(ps, g);
+}
+
+// Batched launch: workgroup i runs item i of a host-built table, a channel
+// group of one stream's window (its descriptor), or nothing (padding).  Items
+// are laid out so that XCD i % 8 holds a contiguous slab of every stream's
+// groups.  At its end each workgroup raises its stream's completion stamp
+// (the device's 100 MHz clock) with an atomic max.
+template <int K, int L>
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L == 64 ? 3 : 1)))
+fwd_batch_kernel(BatchParams) {
+  const FILARK_CONST BatchParams *bp = dev::kparams<BatchParams>();
+  const FILARK_CONST BatchItem *it = (const FILARK_CONST BatchItem *)bp->items + blockIdx.x;
+  const int desc = it->desc;
+  if (desc < 0) return;  // padding, whole workgroup
+  const PSrc ps{(kparams_t)(bp->descs + desc)};
+  fwd_body<K, L, false, true>(ps, it->group);
+  unsigned long long *stamps = bp->stamps;
+  if (stamps) {
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(stamps + it->stream, (unsigned long long)__builtin_amdgcn_s_memrealtime());
+  }
+}
+
+// Clear the completion stamps of n streams and record the start stamp in
+// slot n (a fill kernel, so the reset can live in a captured graph).
+__global__ void __launch_bounds__(256) stamp_reset_kernel(unsigned long long *stamps, int n) {
+  for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) stamps[i] = 0ull;
+  if (threadIdx.x == 0) stamps[n] = (unsigned long long)__builtin_amdgcn_s_memrealtime();
+}
+
+template <int K, int L>
+hipError_t launch_batch_k(const BatchParams &bp, int n_items, int nw, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL((fwd_batch_kernel<K, L>), dim3((unsigned)n_items), dim3((unsigned)(nw * kWave)), lds,
+                     stream, bp);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_batch_l(const BatchParams &bp, int K, int n_items, int nw, size_t lds, hipStream_t stream) {
+  switch (K) {
+    case 1: return launch_batch_k<1, L>(bp, n_items, nw, lds, stream);
+    case 2: return launch_batch_k<2, L>(bp, n_items, nw, lds, stream);
+    case 3: return launch_batch_k<3, L>(bp, n_items, nw, lds, stream);
+    case 4: return launch_batch_k<4, L>(bp, n_items, nw, lds, stream);
+    case 5: return launch_batch_k<5, L>(bp, n_items, nw, lds, stream);
+    case 6: return launch_batch_k<6, L>(bp, n_items, nw, lds, stream);
+    case 7: return launch_batch_k<7, L>(bp, n_items, nw, lds, stream);
+    case 8: return launch_batch_k<8, L>(bp, n_items, nw, lds, stream);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -371,6 +441,20 @@ hipError_t launch_l(const FwdParams &p, int K, bool stalta, bool write_y, hipStr
 }
 
 }  // namespace
+
+hipError_t launch_fwd_batch(const BatchParams &bp, int K, int L, int n_items, int nw, int max_lev,
+                            hipStream_t stream) {
+  if (n_items < 1 || nw < 1 || nw > kMaxWaves || max_lev < 1 || max_lev > kMaxLevels) return hipErrorInvalidValue;
+  const size_t lds = fwd_lds_bytes(K, nw, max_lev);
+  if (L == 32) return launch_batch_l<32>(bp, K, n_items, nw, lds, stream);
+  if (L == 64) return launch_batch_l<64>(bp, K, n_items, nw, lds, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_stamp_reset(unsigned long long *stamps, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(stamp_reset_kernel, dim3(1), dim3(256), 0, stream, stamps, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, hipStream_t stream) {
   if (p.nw < 1 || p.nw > kMaxWaves || p.n_t < 1 || p.n_lev < 1 || p.n_lev > kMaxLevels)

@@ -75,11 +75,30 @@ struct AdjParams {
   int64_t nlta;
 };
 
+// Batched forward launch (SOS only): workgroup i runs items[i], a channel
+// group of the window described by descs[desc] (desc < 0: padding), and
+// raises stamps[stream] to its completion time.
+struct BatchItem {
+  int32_t desc, group, stream, pad;
+};
+struct BatchParams {
+  const FwdParams *descs;
+  const BatchItem *items;
+  unsigned long long *stamps;  // [n_streams + 1] or nullptr
+};
+
 // Dynamic LDS bytes of a forward workgroup.
 size_t fwd_lds_bytes(int K, int nw, int n_lev);
 
 // Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only.
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, hipStream_t stream);
+
+// Batched launch of n_items workgroups of nw waves for K sections and
+// L-sample blocks (max_lev: the most scan levels among the descriptors), and
+// the fill kernel that clears n completion stamps and records the start.
+hipError_t launch_fwd_batch(const BatchParams &bp, int K, int L, int n_items, int nw, int max_lev,
+                            hipStream_t stream);
+hipError_t launch_stamp_reset(unsigned long long *stamps, int n, hipStream_t stream);
 
 // Channel groups per XCD slab and workgroups launched for n_grp groups.
 inline int per_xcd_for(int n_grp) { return (n_grp + 7) / 8; }
