@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
   }
-  __syncthreads();  // level matrices and the checkpointed state are in LDS
+  lds_barrier();  // level matrices and the checkpointed state are in LDS
 
   // ---------------- forward recompute: filter ----------------
   float yk[K][L];                 // output of section k at each row of the block
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     for (int d = 1; d < NB; d <<= 1, ++lev) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) xme[i] = a[i];
-      __syncthreads();
+      lds_barrier();
       if (b >= d) {
         const double *src = xme - d * CW * NSP;
         double t[NS];
@@ -170,18 +170,18 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
         for (int i = 0; i < NS; ++i) t[i] = src[i];
         mv_acc<NS>(pw + lev * NS * NS, t, a);
       }
-      __syncthreads();
+      lds_barrier();
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i) xme[i] = a[i];
-    __syncthreads();
+    lds_barrier();
     double z[NS];
     {
       const double *src = b == 0 ? zc + cl * NSP : xme - CW * NSP;
 #pragma unroll
       for (int i = 0; i < NS; ++i) z[i] = src[i];
     }
-    __syncthreads();  // the exchange is reused below
+    lds_barrier();  // the exchange is reused below
     aparams_t q = aparams();
     cdouble *coef = as_const(q->coef);
     const double asd = q->asd, ald = q->ald;
@@ -230,22 +230,22 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     for (int d = 1; d < NB; d <<= 1, ++lev) {
       xsl[2 * my] = s;
       xsl[2 * my + 1] = l;
-      __syncthreads();
+      lds_barrier();
       if (b >= d) {
         s = fma(dp[2 * lev], xsl[2 * (my - d * CW)], s);
         l = fma(dp[2 * lev + 1], xsl[2 * (my - d * CW) + 1], l);
       }
-      __syncthreads();
+      lds_barrier();
     }
     xsl[2 * my] = s;
     xsl[2 * my + 1] = l;
-    __syncthreads();
+    lds_barrier();
     double Sin = S0, Lin = L0;
     if (b > 0) {
       Sin = xsl[2 * (my - CW)];
       Lin = xsl[2 * (my - CW) + 1];
     }
-    __syncthreads();
+    lds_barrier();
     // through this block's nv valid rows (fewer than L only at the window end)
     cdouble *rp = as_const(q->dpow) + 2 * (q->n_lev + nv);
     Se = fma(rp[0], Sin, s_loc);
@@ -275,16 +275,16 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     for (int d = 1; d < NB; d <<= 1, ++lev) {
       xsl[2 * my] = A;
       xsl[2 * my + 1] = B;
-      __syncthreads();
+      lds_barrier();
       if (b + d < NB) {
         A = fma(dp[2 * lev], xsl[2 * (my + d * CW)], A);
         B = fma(dp[2 * lev + 1], xsl[2 * (my + d * CW) + 1], B);
       }
-      __syncthreads();
+      lds_barrier();
     }
     xsl[2 * my] = A;
     xsl[2 * my + 1] = B;
-    __syncthreads();
+    lds_barrier();
     // exact adjoint after the block: the next block's start, or the
     // handed-in state for the block holding the last row
     double Ax = 0.0, Bx = 0.0;
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       Ax = q->adj[NS * n_ch + c];
       Bx = q->adj[(NS + 1) * n_ch + c];
     }
-    __syncthreads();
+    lds_barrier();
     double S = Se, Lg = Le;
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
@@ -339,7 +339,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     for (int d = 1; d < NB; d <<= 1, ++lev) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) xme[i] = u[i];
-      __syncthreads();
+      lds_barrier();
       if (b + d < NB) {
         const double *src = xme + d * CW * NSP;
         double t[NS];
@@ -347,11 +347,11 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
         for (int i = 0; i < NS; ++i) t[i] = src[i];
         mtv_acc<NS>(pw + lev * NS * NS, t, u);
       }
-      __syncthreads();
+      lds_barrier();
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i) xme[i] = u[i];
-    __syncthreads();
+    lds_barrier();
     if (b < b_end) {
       const double *src = xme + CW * NSP;
 #pragma unroll
@@ -360,7 +360,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) u[i] = (b == b_end && cval) ? q->adj[i * n_ch + c] : 0.0;
     }
-    __syncthreads();  // the adjoint state is overwritten below
+    lds_barrier();  // the adjoint state is overwritten below
 
     // rerun from the exact end state: dL/dx and the coefficient gradients
     double gc[NC];
@@ -407,7 +407,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
       if (lane == 0) wsum[w * NC + i] = v;
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x < NC) {
       double s = 0.0;
       for (int v = 0; v < NW; ++v) s += wsum[v * NC + threadIdx.x];

@@ -46,6 +46,16 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, 0, 0);
 }
 
+// Workgroup barrier for data exchanged through LDS only: each wave waits for
+// its own LDS operations, then all waves meet.  Unlike __syncthreads() it
+// does not wait for outstanding global loads and stores, which the kernels
+// never exchange between waves of a workgroup (global values read before a
+// barrier are consumed before it), so stores keep draining and prefetched
+// loads keep arriving across the scans.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // acc += M v for a block-lower-triangular M [NS][NS] (2x2 diagonal blocks)
 // held in LDS; all lanes read the same entries (broadcast).  The fences keep
 // one row of M in registers at a time.

@@ -41,11 +41,11 @@ namespace filark {
 
 // Dynamic LDS of one workgroup, all FP64: filter scan exchange
 // [nw * 64][2K + 1] (the odd row pitch spreads a wave's rows over the banks),
-// STA/LTA exchange [nw * 64][2], level matrices [n_lev][2K][2K] and the
-// carried filter state [64][2K + 1].
+// STA/LTA exchange [nw * 64][2], level matrices [n_lev][2K][2K], and the
+// staged carried state: filter [64][2K + 1], STA/LTA sums [64][2].
 size_t fwd_lds_bytes(int K, int nw, int n_lev) {
   const int NS = 2 * K, NSP = NS + 1;
-  return ((size_t)nw * kWave * (NSP + 2) + (size_t)n_lev * NS * NS + (size_t)kWave * NSP) *
+  return ((size_t)nw * kWave * (NSP + 2) + (size_t)n_lev * NS * NS + (size_t)kWave * (NSP + 2)) *
          sizeof(double);
 }
 
@@ -187,10 +187,105 @@ __device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, f
   }
 }
 
-// One workgroup's work: channel group g of the stream described by ps, over
-// one window of rows.
+// LDS regions of a forward workgroup (see fwd_lds_bytes).
+struct FwdLds {
+  double *xsl, *xch, *pw, *zc, *slc;
+  __device__ __forceinline__ FwdLds(kparams_t p, int NS) {
+    extern __shared__ double lds[];
+    const int NSP = NS + 1, n = p->nw * kWave;
+    xsl = lds;                        // [n][2]
+    xch = xsl + 2 * n;                // [n][NSP]
+    pw = xch + n * NSP;               // [n_lev][NS][NS]
+    zc = pw + p->n_lev * NS * NS;     // [64][NSP]
+    slc = zc + kWave * NSP;           // [64][2]
+  }
+};
+
+// The carried state of channel group g, read by the lanes of block 0 before
+// any signal load is issued: a later wait for it then never waits for the
+// signal loads or for stores (the vector-memory counter is in order).
+template <int K, bool STALTA>
+struct Staged {
+  double z[2 * K > 0 ? 2 * K : 1];
+  double s, l;
+  __device__ __forceinline__ void read(PSrc ps, int g) {
+    kparams_t p = ps.get();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int cwl = p->cw_log2, CW = 1 << cwl;
+    const int b = uniform(threadIdx.x / kWave) * (kWave >> cwl) + (lane >> cwl);
+    const int64_t n_ch = p->n_ch;
+    const int64_t c = (int64_t)g * CW + (lane & (CW - 1));
+    const bool on = b == 0 && c < n_ch;
+#pragma unroll
+    for (int i = 0; i < 2 * K; ++i) z[i] = on ? p->zs[i * n_ch + c] : 0.0;
+    s = 0.0;
+    l = 0.0;
+    if constexpr (STALTA) {
+      if (on) {
+        s = p->sl[c] * p->nsta_d;
+        l = p->sl[n_ch + c] * p->nlta_d;
+      }
+    }
+  }
+  // into LDS (after the signal loads have been issued)
+  __device__ __forceinline__ void write(PSrc ps, const FwdLds &m) const {
+    kparams_t p = ps.get();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int cwl = p->cw_log2, CW = 1 << cwl;
+    const int b = uniform(threadIdx.x / kWave) * (kWave >> cwl) + (lane >> cwl);
+    const int cl = lane & (CW - 1);
+    constexpr int NSP = 2 * K + 1;
+    if (b == 0) {
+#pragma unroll
+      for (int i = 0; i < 2 * K; ++i) m.zc[cl * NSP + i] = z[i];
+      if constexpr (STALTA) {
+        m.slc[cl * 2 + 0] = s;
+        m.slc[cl * 2 + 1] = l;
+      }
+    }
+  }
+};
+
+// Level matrices into LDS (once per workgroup).
+template <int K>
+__device__ __forceinline__ void stage_levels(PSrc ps, const FwdLds &m) {
+  constexpr int NS = 2 * K;
+  if constexpr (K > 0) {
+    kparams_t p = ps.get();
+    const int n = p->n_lev * NS * NS;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) m.pw[k] = p->Pw[k];
+  }
+}
+
+// Loads of channel group g's window into xv (issued, not waited for).
+template <int L>
+__device__ __forceinline__ void fwd_load(PSrc ps, int g, float (&xv)[L]) {
+  kparams_t p = ps.get();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = uniform(threadIdx.x / kWave);
+  const int cwl = p->cw_log2;
+  const int CW = 1 << cwl, R = kWave >> cwl;
+  const int r = lane >> cwl, cl = lane & (CW - 1);
+  const int b = w * R + r;
+  const int64_t n_ch = p->n_ch;
+  const int64_t c = (int64_t)g * CW + cl;
+  const bool cval = c < n_ch;
+  const uint32_t rowb = (uint32_t)n_ch * 4u;
+  const int64_t row0 = (int64_t)b * L;
+  const uint32_t vo = cval ? (uint32_t)((row0 * n_ch + c) * 4) : kOffInvalid;
+  const __amdgpu_buffer_rsrc_t rx = rsrc(ps.get()->x, ps.get()->range);
+  const uint32_t rb = fresh(rowb);
+#pragma unroll
+  for (int j = 0; j < L; ++j) {
+    xv[j] = buf_ld(rx, vo + (uint32_t)j * rb);
+    if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Everything after the loads for channel group g of the stream described by
+// ps, over one window of rows: carries, passes, stores, carried state.
 template <int K, int L, bool STALTA, bool WRITE_Y>
-__device__ __forceinline__ void fwd_body(PSrc ps, int g) {
+__device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
   constexpr int NS = 2 * K;
   extern __shared__ double lds[];
   kparams_t p = ps.get();
@@ -206,19 +301,13 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   const int64_t n_ch = p->n_ch;
   const int64_t c = (int64_t)g * CW + cl;
   const bool cval = c < n_ch;
-  double *xsl = lds;                       // [NW * 64][2] STA/LTA scan exchange
-  double *xch = xsl + 2 * NW * kWave;      // [NW * 64][NSP] filter scan exchange
-  double *pw = xch + NW * kWave * NSP;     // [n_lev][NS][NS]
-  double *zc = pw + p->n_lev * NS * NS;    // [CW][NSP] carried state at the window start
+  const FwdLds m(p, NS);
+  double *xsl = m.xsl;                     // [NW * 64][2] STA/LTA scan exchange
+  double *xch = m.xch;                     // [NW * 64][NSP] filter scan exchange
+  double *pw = m.pw;                       // [n_lev][NS][NS]
+  double *zc = m.zc;                       // [CW][NSP] carried state at the window start
+  const double *slc = m.slc;               // [CW][2] carried STA/LTA sums
   double *xme = xch + my * NSP;            // this lane's exchange row
-  if constexpr (K > 0) {
-    const int n = p->n_lev * NS * NS;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) pw[k] = p->Pw[k];
-    if (b == 0) {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) zc[cl * NSP + i] = cval ? p->zs[i * n_ch + c] : 0.0;
-    }
-  }
 
   // the window's last row: block, wave and row within the block
   const int n_t = p->n_t;
@@ -231,18 +320,8 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   const int64_t row0 = (int64_t)b * L;
   const uint32_t vo = cval ? (uint32_t)((row0 * n_ch + c) * 4) : kOffInvalid;
 
-  float xv[L];
-  {
-    const __amdgpu_buffer_rsrc_t rx = rsrc(ps.get()->x, ps.get()->range);
-    const uint32_t rb = fresh(rowb);
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      xv[j] = buf_ld(rx, vo + (uint32_t)j * rb);
-      if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
-    }
-  }
   double s_loc = 0.0, l_loc = 0.0, sc = 0.0, lc = 0.0;
-  __syncthreads();  // level matrices and the carried state are in LDS
+  lds_barrier();  // level matrices and the staged carried state are in LDS
 
   if constexpr (K > 0) {
     double a[NS];
@@ -257,7 +336,7 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
     for (int d = 1; d < NB; d <<= 1, ++lev) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) xme[i] = a[i];
-      __syncthreads();
+      lds_barrier();
       if (b >= d) {
         const double *src = xme - d * CW * NSP;
         double t[NS];
@@ -265,11 +344,11 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
         for (int i = 0; i < NS; ++i) t[i] = src[i];
         mv_acc<NS>(pw + lev * NS * NS, t, a);
       }
-      __syncthreads();
+      lds_barrier();
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i) xme[i] = a[i];
-    __syncthreads();
+    lds_barrier();
     // entry state of the block: the state after block b - 1
     double z[NS];
     {
@@ -277,7 +356,7 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
 #pragma unroll
       for (int i = 0; i < NS; ++i) z[i] = src[i];
     }
-    __syncthreads();  // the capture below reuses the exchange
+    lds_barrier();  // the capture below reuses the exchange
     {
       kparams_t q = ps.get();
       const __amdgpu_buffer_rsrc_t ry =
@@ -294,15 +373,12 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   }
 
   if constexpr (STALTA) {
-    int64_t g0 = 0;
+    // the sample counter is equal for all channels: one scalar load
+    const int64_t g0 = ((const FILARK_CONST int64_t *)ps.get()->cnt)[(int64_t)g * CW];
     double S0 = 0.0, L0 = 0.0;
-    if (cval) {
-      kparams_t q = ps.get();
-      g0 = q->cnt[c];
-      if (b == 0) {
-        S0 = q->sl[c] * q->nsta_d;
-        L0 = q->sl[n_ch + c] * q->nlta_d;
-      }
+    if (b == 0) {
+      S0 = slc[cl * 2 + 0];
+      L0 = slc[cl * 2 + 1];
     }
     {
       cdouble *dp = as_const(ps.get()->dpow);
@@ -314,18 +390,18 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
       for (int d = 1; d < NB; d <<= 1, ++lev) {
         xsl[2 * my] = s_loc;
         xsl[2 * my + 1] = l_loc;
-        __syncthreads();
+        lds_barrier();
         if (b >= d) {
           const double ts = xsl[2 * (my - d * CW)], tl = xsl[2 * (my - d * CW) + 1];
           s_loc = fma(dp[2 * lev], ts, s_loc);
           l_loc = fma(dp[2 * lev + 1], tl, l_loc);
         }
-        __syncthreads();
+        lds_barrier();
       }
     }
     xsl[2 * my] = s_loc;
     xsl[2 * my + 1] = l_loc;
-    __syncthreads();
+    lds_barrier();
     double Sin = S0, Lin = L0;
     if (b > 0) {
       Sin = xsl[2 * (my - CW)];
@@ -348,6 +424,21 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   }
 }
 
+template <int K, int L, bool STALTA, bool WRITE_Y>
+__device__ __forceinline__ void fwd_body(PSrc ps, int g) {
+  const FwdLds m(ps.get(), 2 * K);
+  Staged<K, STALTA> sa;
+  sa.read(ps, g);
+  stage_levels<K>(ps, m);
+  float xv[L];
+  fwd_load<L>(ps, g, xv);
+  sa.write(ps, m);
+  fwd_compute<K, L, STALTA, WRITE_Y>(ps, g, xv);
+}
+
+// One channel group per workgroup.  Three waves per SIMD for 64-sample blocks
+// (at most 168 VGPRs), so that every workgroup of a 6000-channel chunk is
+// resident at once.
 template <int K, int L, bool STALTA, bool WRITE_Y>
 __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L == 64 ? 3 : 1)))
 fwd_kernel(FwdParams) {
@@ -373,7 +464,7 @@ fwd_batch_kernel(BatchParams) {
   fwd_body<K, L, false, true>(ps, it->group);
   unsigned long long *stamps = bp->stamps;
   if (stamps) {
-    __syncthreads();
+    __syncthreads();  // every wave's stores have completed
     if (threadIdx.x == 0) atomicMax(stamps + it->stream, (unsigned long long)__builtin_amdgcn_s_memrealtime());
   }
 }
