@@ -64,16 +64,15 @@ struct SlBack {
   double cs, cl, asd, ald, ias, ial, scale;
   int64_t nlta;
   int mode;
-  __device__ __forceinline__ double step(double &A, double &B, double &S, double &Lg, float yf,
-                                         float gq, int64_t gidx) const {
+  __device__ __forceinline__ double step(double &A, double &B, double &S, double &Lg, double yd,
+                                         double gq, int64_t gidx) const {
     const double sta = S * cs, lta = Lg * cl;
     const bool live = gidx >= nlta && lta > 0.0;
     const double rl = live ? 1.0 / lta : 0.0;
     const double cf = sta * rl;
-    const double q = live ? (mode ? 2.0 * scale * (cf - (double)gq) : (double)gq) : 0.0;
+    const double q = live ? (mode ? 2.0 * scale * (cf - gq) : gq) : 0.0;
     const double Sb = fma(q, rl, A);
     const double Lb = fma(-q * cf, rl, B);
-    const double yd = (double)yf;
     const double e = yd * yd;
     const double ybar = 2.0 * yd * fma(cs, Sb, cl * Lb);
     A = asd * Sb;
@@ -187,7 +186,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     const double asd = q->asd, ald = q->ald;
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-      double v = (double)xv[j];
+      double v = widen<1>(xv[j]);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const double yy = fma(coef[5 * k + 0], v, z[2 * k]);
@@ -197,7 +196,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
         v = yy;
       }
       // sums from the rounded output, the value the backward pass sees
-      const double yd = (double)yk[K - 1][j];
+      const double yd = widen<2>(yk[K - 1][j]);
       const double e = yd * yd;
       if (j < nv) {
         s_loc = fma(asd, s_loc, e);
@@ -266,7 +265,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       double S = Se, Lg = Le;
 #pragma unroll
       for (int j = L - 1; j >= 0; --j) {
-        if (j < nv) sb.step(A, B, S, Lg, yk[K - 1][j], gv[j], g0 + row0 + j);
+        if (j < nv) sb.step(A, B, S, Lg, widen<3>(yk[K - 1][j]), widen<4>(gv[j]), g0 + row0 + j);
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -300,7 +299,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
       float v = 0.0f;
-      if (j < nv) v = (float)sb.step(Ax, Bx, S, Lg, yk[K - 1][j], gv[j], g0 + row0 + j);
+      if (j < nv) v = (float)sb.step(Ax, Bx, S, Lg, widen<5>(yk[K - 1][j]), widen<6>(gv[j]), g0 + row0 + j);
       yb[j] = v;
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -370,12 +369,12 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     const uint32_t rb = fresh(rowb);
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
-      double ybar = (double)yb[j];
+      double ybar = widen<7>(yb[j]);
       if (j < nv) {
 #pragma unroll
         for (int k = K - 1; k >= 0; --k) {
-          const double vin = k == 0 ? (double)xv[j] : (double)yk[k - 1][j];
-          const double yout = (double)yk[k][j];
+          const double vin = k == 0 ? widen<8>(xv[j]) : widen<9>(yk[k - 1][j]);
+          const double yout = widen<9>(yk[k][j]);
           const double u1 = u[2 * k], u2 = u[2 * k + 1];
           const double ys = fma(coef[5 * k + 4], u2, fma(coef[5 * k + 3], u1, ybar));
           gc[5 * k + 0] = fma(ys, vin, gc[5 * k + 0]);

@@ -22,6 +22,15 @@ __device__ __forceinline__ uint32_t fresh(uint32_t v) {
   return v;
 }
 
+// FP64 value of a register-resident float, opaque to the compiler: each call
+// site (its TAG) converts afresh, so the conversions of one phase are not
+// kept live (two registers each) to be reused by a later phase.
+template <int TAG>
+__device__ __forceinline__ double widen(float x) {
+  asm("; widen %1" : "+v"(x) : "n"(TAG));
+  return (double)x;
+}
+
 // Kernel parameters are read through the kernarg-segment pointer, taken
 // afresh in every phase: each phase scalar-loads only the fields it uses,
 // and nothing from the parameter block stays live across other phases.

@@ -120,7 +120,7 @@ __device__ __forceinline__ void pass2(PSrc ps, float (&xv)[L], double (&z)[2 * K
   }
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    double v = (double)xv[j];
+    double v = widen<1>(xv[j]);  // not pass 1's conversion, held until now
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const double yk = fma(cb0[k], v, z[2 * k]);
