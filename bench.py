@@ -195,7 +195,7 @@ def batched_leg(F, torch, dev, replays: int, parity: bool):
     from paper_2605_20132_amd.autotune import Autotuner
 
     specs = synth.draw_batched_streams()
-    tuner = Autotuner(None, block=64, waves=4, reps=3)
+    tuner = Autotuner(None, block=48, waves=4, reps=3)
     sts, xs, ys, soss = [], [], [], []
     for sp in specs:
         sos = F.sos_design(sp.order, "bandpass", sp.f1, sp.f2, sp.fs)

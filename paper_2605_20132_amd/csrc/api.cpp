@@ -48,10 +48,12 @@ filark_status fail(filark_status st, const char *fmt, ...) {
     if (e_ != hipSuccess) return fail(FILARK_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-// Default tile: 64-sample blocks, 3 waves, groups of 8 channels, i.e. one
-// workgroup covers 1536 rows of 8 channels per window.
-constexpr int kDefaultBlock = 64;
-constexpr int kDefaultWaves = 3;
+// Default tile: 48-sample blocks, 4 waves, groups of 8 channels, i.e. one
+// workgroup covers 1536 rows of 8 channels per window.  Three such
+// workgroups fill a CU with 12 waves, three on each SIMD: the VALU-bound
+// passes see no SIMD with more waves than the others.
+constexpr int kDefaultBlock = 48;
+constexpr int kDefaultWaves = 4;
 constexpr int kDefaultGroup = 8;
 
 struct Tile {
@@ -362,7 +364,7 @@ filark_status run_forward(filark_sos_state *sos, filark_stalta_state *sl, const 
                 (long long)n_ch, t.window(), (long long)(0x7fffffffull / (uint64_t)t.window() / 4u));
   const int K = sos ? sos->cas.K : 0;
   const int dev = sos ? sos->device : sl->device;
-  filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels()), t, K, dev);
+  filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels(), t.group), t, K, dev);
   if (rc != FILARK_OK) return rc;
   const int prev_dev = current_device();
   if (prev_dev != dev) HIP_TRY(hipSetDevice(dev));
@@ -397,8 +399,8 @@ filark_status grow_raw(T **buf, size_t *have, size_t need) {
 }
 
 filark_status check_tile(int block, int waves, int group, bool adjoint) {
-  if (adjoint ? (block != 8 && block != 16) : (block != 32 && block != 64))
-    return fail(FILARK_EINVAL, adjoint ? "adjoint block must be 8 or 16" : "block must be 32 or 64");
+  if (adjoint ? (block != 8 && block != 16) : (block != 32 && block != 48 && block != 64))
+    return fail(FILARK_EINVAL, adjoint ? "adjoint block must be 8 or 16" : "block must be 32, 48 or 64");
   if (waves < 1 || waves > kMaxWaves) return fail(FILARK_EINVAL, "waves must be in [1, %d]", kMaxWaves);
   if (group != 4 && group != 8 && group != 16 && group != 32 && group != 64)
     return fail(FILARK_EINVAL, "group must be 4, 8, 16, 32 or 64 channels");
@@ -714,7 +716,7 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
   const int64_t rows = launch_rows(ta, n_ch);
   if (rows == 0 || launch_rows(tf, n_ch) == 0) return fail(FILARK_EINVAL, "n_ch %lld too large", (long long)n_ch);
   filark_status rc = check_lds(adj_lds_bytes(K, ta.waves, ta.levels()), ta, K, sos->device);
-  if (rc == FILARK_OK) rc = check_lds(fwd_lds_bytes(K, tf.waves, tf.levels()), tf, K, sos->device);
+  if (rc == FILARK_OK) rc = check_lds(fwd_lds_bytes(K, tf.waves, tf.levels(), tf.group), tf, K, sos->device);
   if (rc != FILARK_OK) return rc;
   const int prev_dev = current_device();
   if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
@@ -839,7 +841,7 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
     const int64_t rows = launch_rows(t, st->n_ch);
     if (rows == 0) return fail(FILARK_EINVAL, "stream %d: n_ch too large for its tile", s);
     const int K = st->cas.K;
-    filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels()), t, K, b->device);
+    filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels(), kWave), t, K, b->device);
     if (rc != FILARK_OK) return rc;
     const uint64_t rowb = (uint64_t)st->n_ch * 4u;
     for (int64_t t0 = 0, r = 0; t0 < n_t[s]; t0 += rows, ++r) {

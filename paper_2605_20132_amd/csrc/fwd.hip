@@ -42,10 +42,11 @@ namespace filark {
 // Dynamic LDS of one workgroup, all FP64: filter scan exchange
 // [nw * 64][2K + 1] (the odd row pitch spreads a wave's rows over the banks),
 // STA/LTA exchange [nw * 64][2], level matrices [n_lev][2K][2K], and the
-// staged carried state: filter [64][2K + 1], STA/LTA sums [64][2].
-size_t fwd_lds_bytes(int K, int nw, int n_lev) {
+// staged carried state of the cw channels: filter [cw][2K + 1], STA/LTA sums
+// [cw][2].
+size_t fwd_lds_bytes(int K, int nw, int n_lev, int cw) {
   const int NS = 2 * K, NSP = NS + 1;
-  return ((size_t)nw * kWave * (NSP + 2) + (size_t)n_lev * NS * NS + (size_t)kWave * (NSP + 2)) *
+  return ((size_t)nw * kWave * (NSP + 2) + (size_t)n_lev * NS * NS + (size_t)cw * (NSP + 2)) *
          sizeof(double);
 }
 
@@ -67,32 +68,53 @@ struct PSrc {
   }
 };
 
-// Pass 1: zero-state block-end projection a = sum_j A^(L-1-j) B x_j.  Row j+1
-// of G is fetched into SGPRs while row j is applied; the fences stop the
-// scheduler from hoisting the whole table into SGPRs.
+// Pass 1: zero-state block-end projection a = sum_j A^(L-1-j) B x_j.  The
+// rows of G are scalar-loaded (one fetch per wave) in batches of D rows.
+// Scalar loads complete out of order, so any wait for one waits for all: the
+// next batch is therefore issued only after the first use of the current one
+// (which is where that wait sits), and arrives while the rest of the batch is
+// applied.  The fences keep this order and stop the scheduler from hoisting
+// the whole table into SGPRs.
 template <int K, int L>
 __device__ __forceinline__ void pass1(PSrc ps, const float (&xv)[L], double (&a)[2 * K]) {
   constexpr int NS = 2 * K;
+  constexpr int D = NS >= 16 ? 1 : 16 / NS;  // two batches of D rows: 4 D NS SGPRs
   cdouble *G = as_const(ps.get()->G);
-  double gn[NS];
+  double cur[D][NS], nxt[D][NS];
 #pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    a[i] = 0.0;
-    gn[i] = G[i];
+  for (int i = 0; i < NS; ++i) a[i] = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) cur[d][i] = d < L ? G[d * NS + i] : 0.0;
   }
 #pragma unroll
-  for (int j = 0; j < L; ++j) {
-    double gc[NS];
+  for (int jb = 0; jb < L; jb += D) {
 #pragma unroll
-    for (int i = 0; i < NS; ++i) gc[i] = gn[i];
-    if (j + 1 < L) {
+    for (int d = 0; d < D; ++d) {
+      const int j = jb + d;
+      if (j < L) {
+        const double xd = (double)xv[j];
+        a[0] = fma(cur[d][0], xd, a[0]);
+        if (d == 0) {
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int i = 0; i < NS; ++i) gn[i] = G[(j + 1) * NS + i];
+          for (int e = 0; e < D; ++e) {
+#pragma unroll
+            for (int i = 0; i < NS; ++i) nxt[e][i] = jb + D + e < L ? G[(jb + D + e) * NS + i] : 0.0;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int i = 1; i < NS; ++i) a[i] = fma(cur[d][i], xd, a[i]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
-    const double xd = (double)xv[j];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) a[i] = fma(gc[i], xd, a[i]);
-    __builtin_amdgcn_sched_barrier(0);
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) cur[d][i] = nxt[d][i];
+    }
   }
 }
 
@@ -196,8 +218,8 @@ struct FwdLds {
     xsl = lds;                        // [n][2]
     xch = xsl + 2 * n;                // [n][NSP]
     pw = xch + n * NSP;               // [n_lev][NS][NS]
-    zc = pw + p->n_lev * NS * NS;     // [64][NSP]
-    slc = zc + kWave * NSP;           // [64][2]
+    zc = pw + p->n_lev * NS * NS;     // [CW][NSP]
+    slc = zc + (NSP << p->cw_log2);   // [CW][2]
   }
 };
 
@@ -246,16 +268,38 @@ struct Staged {
   }
 };
 
-// Level matrices into LDS (once per workgroup).
+// Level matrices into LDS.  Up to kCap values per thread are read into
+// registers before the signal loads are issued and written to LDS after, so
+// no wait for these reads holds back the signal loads; any remainder (many
+// levels on a narrow workgroup) is copied afterwards.
 template <int K>
-__device__ __forceinline__ void stage_levels(PSrc ps, const FwdLds &m) {
-  constexpr int NS = 2 * K;
-  if constexpr (K > 0) {
-    kparams_t p = ps.get();
-    const int n = p->n_lev * NS * NS;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) m.pw[k] = p->Pw[k];
+struct Levels {
+  static constexpr int NS = 2 * K, kCap = 4;
+  double v[kCap];
+  __device__ __forceinline__ void read(PSrc ps) {
+    if constexpr (K > 0) {
+      kparams_t p = ps.get();
+      const int n = p->n_lev * NS * NS;
+#pragma unroll
+      for (int i = 0; i < kCap; ++i) {
+        const int k = (int)threadIdx.x + i * (int)blockDim.x;
+        v[i] = k < n ? p->Pw[k] : 0.0;
+      }
+    }
   }
-}
+  __device__ __forceinline__ void write(PSrc ps, const FwdLds &m) const {
+    if constexpr (K > 0) {
+      kparams_t p = ps.get();
+      const int n = p->n_lev * NS * NS;
+#pragma unroll
+      for (int i = 0; i < kCap; ++i) {
+        const int k = (int)threadIdx.x + i * (int)blockDim.x;
+        if (k < n) m.pw[k] = v[i];
+      }
+      for (int k = (int)threadIdx.x + kCap * (int)blockDim.x; k < n; k += (int)blockDim.x) m.pw[k] = p->Pw[k];
+    }
+  }
+};
 
 // Loads of channel group g's window into xv (issued, not waited for).
 template <int L>
@@ -428,19 +472,21 @@ template <int K, int L, bool STALTA, bool WRITE_Y>
 __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   const FwdLds m(ps.get(), 2 * K);
   Staged<K, STALTA> sa;
+  Levels<K> tb;
   sa.read(ps, g);
-  stage_levels<K>(ps, m);
+  tb.read(ps);
   float xv[L];
   fwd_load<L>(ps, g, xv);
   sa.write(ps, m);
+  tb.write(ps, m);
   fwd_compute<K, L, STALTA, WRITE_Y>(ps, g, xv);
 }
 
-// One channel group per workgroup.  Three waves per SIMD for 64-sample blocks
-// (at most 168 VGPRs), so that every workgroup of a 6000-channel chunk is
-// resident at once.
+// One channel group per workgroup.  Three waves per SIMD for 48- and 64-sample
+// blocks (at most 168 VGPRs), so that every workgroup of a 6000-channel chunk
+// is resident at once.
 template <int K, int L, bool STALTA, bool WRITE_Y>
-__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L == 64 ? 3 : 1)))
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L >= 48 ? 3 : 1)))
 fwd_kernel(FwdParams) {
   const PSrc ps{dev::kparams<FwdParams>()};
   const int g = group_of(ps.get()->per_xcd);
@@ -454,7 +500,7 @@ fwd_kernel(FwdParams) {
 // groups.  At its end each workgroup raises its stream's completion stamp
 // (the device's 100 MHz clock) with an atomic max.
 template <int K, int L>
-__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L == 64 ? 3 : 1)))
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L >= 48 ? 3 : 1)))
 fwd_batch_kernel(BatchParams) {
   const FILARK_CONST BatchParams *bp = dev::kparams<BatchParams>();
   const FILARK_CONST BatchItem *it = (const FILARK_CONST BatchItem *)bp->items + blockIdx.x;
@@ -500,7 +546,7 @@ hipError_t launch_batch_l(const BatchParams &bp, int K, int n_items, int nw, siz
 
 template <int K, int L, bool S, bool Y>
 hipError_t launch_one(const FwdParams &p, hipStream_t stream) {
-  const size_t lds = fwd_lds_bytes(K, p.nw, p.n_lev);
+  const size_t lds = fwd_lds_bytes(K, p.nw, p.n_lev, 1 << p.cw_log2);
   const dim3 grid((unsigned)fwd_grid(p));
   const dim3 block((unsigned)(p.nw * kWave));
   hipLaunchKernelGGL((fwd_kernel<K, L, S, Y>), grid, block, lds, stream, p);
@@ -536,8 +582,9 @@ hipError_t launch_l(const FwdParams &p, int K, bool stalta, bool write_y, hipStr
 hipError_t launch_fwd_batch(const BatchParams &bp, int K, int L, int n_items, int nw, int max_lev,
                             hipStream_t stream) {
   if (n_items < 1 || nw < 1 || nw > kMaxWaves || max_lev < 1 || max_lev > kMaxLevels) return hipErrorInvalidValue;
-  const size_t lds = fwd_lds_bytes(K, nw, max_lev);
+  const size_t lds = fwd_lds_bytes(K, nw, max_lev, kWave);  // any stream's group
   if (L == 32) return launch_batch_l<32>(bp, K, n_items, nw, lds, stream);
+  if (L == 48) return launch_batch_l<48>(bp, K, n_items, nw, lds, stream);
   if (L == 64) return launch_batch_l<64>(bp, K, n_items, nw, lds, stream);
   return hipErrorInvalidValue;
 }
@@ -551,6 +598,7 @@ hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_
   if (p.nw < 1 || p.nw > kMaxWaves || p.n_t < 1 || p.n_lev < 1 || p.n_lev > kMaxLevels)
     return hipErrorInvalidValue;
   if (L == 32) return launch_l<32>(p, K, stalta, write_y, stream);
+  if (L == 48) return launch_l<48>(p, K, stalta, write_y, stream);
   if (L == 64) return launch_l<64>(p, K, stalta, write_y, stream);
   return hipErrorInvalidValue;
 }

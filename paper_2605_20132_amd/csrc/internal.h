@@ -88,7 +88,7 @@ struct BatchParams {
 };
 
 // Dynamic LDS bytes of a forward workgroup.
-size_t fwd_lds_bytes(int K, int nw, int n_lev);
+size_t fwd_lds_bytes(int K, int nw, int n_lev, int cw);
 
 // Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only.
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, hipStream_t stream);

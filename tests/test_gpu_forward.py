@@ -241,7 +241,7 @@ def test_shape_errors(F):
         F.SOSState(np.array([[1.0, 0, 0, 1.0, -2.0, 1.0]]), 4)  # double pole at z = 1
 
 
-@pytest.mark.parametrize("block", [32, 64])
+@pytest.mark.parametrize("block", [32, 48, 64])
 @pytest.mark.parametrize("waves", [1, 3, 8])
 @pytest.mark.parametrize("group", [4, 8, 16, 64])
 def test_tile_shapes(F, block, waves, group):
@@ -281,7 +281,7 @@ def test_tile_shape_errors(F):
     sos = orc.butter_sos(4, "bandpass", 1.0, 50.0, 500.0)
     st = F.SOSState(sos, 64)
     sl = F.StaLtaState(0.1, 1.0, 500.0, 64)
-    for b, w, gr in [(16, 4, 8), (64, 0, 8), (64, 9, 8), (48, 2, 8), (64, 2, 3), (64, 2, 128)]:
+    for b, w, gr in [(16, 4, 8), (64, 0, 8), (64, 9, 8), (40, 2, 8), (64, 2, 3), (64, 2, 128)]:
         with pytest.raises(F.FilarkError) as e:
             st.set_tile(b, w, gr)
         assert e.value.status == F.EINVAL
