@@ -140,17 +140,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
   float yk[K][L];                 // output of section k at each row of the block
   double s_loc = 0.0, l_loc = 0.0;  // STA/LTA sums from zero over the block's valid rows
   {
-    cdouble *G = as_const(aparams()->G);
     double a[NS];
-#pragma unroll
-    for (int i = 0; i < NS; ++i) a[i] = 0.0;
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      const double xd = (double)xv[j];
-#pragma unroll
-      for (int i = 0; i < NS; ++i) a[i] = fma(G[j * NS + i], xd, a[i]);
-      __builtin_amdgcn_sched_barrier(0);
-    }
+    project<K, L>(as_const(aparams()->G), xv, a);
     if (b == 0) {
       double z0[NS];
 #pragma unroll

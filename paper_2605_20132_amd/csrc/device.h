@@ -80,6 +80,39 @@ __device__ __forceinline__ void mv_acc(const double *M, const double (&v)[NS], d
   }
 }
 
+// Entries of the lower block triangle of a block-lower-triangular [NS][NS]
+// matrix (2x2 blocks), row by row: 2K(K+1) for NS = 2K.
+template <int NS>
+constexpr int tri_count() {
+  return (NS / 2) * (NS / 2 + 1) * 2;
+}
+
+// The lower block triangle of a wave-uniform matrix, scalar-loaded (SGPRs:
+// one fetch per wave, where an LDS read would return 64 copies).
+template <int NS>
+__device__ __forceinline__ void tri_load(cdouble *M, double (&m)[tri_count<NS>()]) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+#pragma unroll
+    for (int j = 0; j < (i / 2 + 1) * 2; ++j) m[k++] = M[i * NS + j];
+  }
+}
+
+// acc += M v with M given by tri_load.
+template <int NS>
+__device__ __forceinline__ void tri_mv_acc(const double (&m)[tri_count<NS>()], const double (&v)[NS],
+                                           double (&acc)[NS]) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    double s = acc[i];
+#pragma unroll
+    for (int j = 0; j < (i / 2 + 1) * 2; ++j) s = fma(m[k++], v[j], s);
+    acc[i] = s;
+  }
+}
+
 // acc += M^T v for the same M (block-upper-triangular product).
 template <int NS>
 __device__ __forceinline__ void mtv_acc(const double *M, const double (&v)[NS], double (&acc)[NS]) {
@@ -90,6 +123,57 @@ __device__ __forceinline__ void mtv_acc(const double *M, const double (&v)[NS], 
     for (int i = (j / 2) * 2; i < NS; ++i) s = fma(M[i * NS + j], v[i], s);
     acc[j] = s;
     __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// Zero-state block-end projection a = sum_j A^(L-1-j) B x_j = sum_j G_j x_j
+// of a block of L samples held in registers (G: [L][2K], row j = A^(L-1-j) B).
+// The
+// rows of G are scalar-loaded (one fetch per wave) in batches of D rows.
+// Scalar loads complete out of order, so any wait for one waits for all: the
+// next batch is therefore issued only after the first use of the current one
+// (which is where that wait sits), and arrives while the rest of the batch is
+// applied.  The fences keep this order and stop the scheduler from hoisting
+// the whole table into SGPRs.
+template <int K, int L>
+__device__ __forceinline__ void project(cdouble *G, const float (&xv)[L], double (&a)[2 * K]) {
+  constexpr int NS = 2 * K;
+  constexpr int D = NS >= 16 ? 1 : 16 / NS;  // two batches of D rows: 4 D NS SGPRs
+  double cur[D][NS], nxt[D][NS];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) a[i] = 0.0;
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) cur[d][i] = d < L ? G[d * NS + i] : 0.0;
+  }
+#pragma unroll
+  for (int jb = 0; jb < L; jb += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int j = jb + d;
+      if (j < L) {
+        const double xd = (double)xv[j];
+        a[0] = fma(cur[d][0], xd, a[0]);
+        if (d == 0) {
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int e = 0; e < D; ++e) {
+#pragma unroll
+            for (int i = 0; i < NS; ++i) nxt[e][i] = jb + D + e < L ? G[(jb + D + e) * NS + i] : 0.0;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int i = 1; i < NS; ++i) a[i] = fma(cur[d][i], xd, a[i]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) cur[d][i] = nxt[d][i];
+    }
   }
 }
 

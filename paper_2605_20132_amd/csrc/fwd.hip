@@ -68,54 +68,10 @@ struct PSrc {
   }
 };
 
-// Pass 1: zero-state block-end projection a = sum_j A^(L-1-j) B x_j.  The
-// rows of G are scalar-loaded (one fetch per wave) in batches of D rows.
-// Scalar loads complete out of order, so any wait for one waits for all: the
-// next batch is therefore issued only after the first use of the current one
-// (which is where that wait sits), and arrives while the rest of the batch is
-// applied.  The fences keep this order and stop the scheduler from hoisting
-// the whole table into SGPRs.
+// Pass 1: zero-state block-end projection (dev::project).
 template <int K, int L>
 __device__ __forceinline__ void pass1(PSrc ps, const float (&xv)[L], double (&a)[2 * K]) {
-  constexpr int NS = 2 * K;
-  constexpr int D = NS >= 16 ? 1 : 16 / NS;  // two batches of D rows: 4 D NS SGPRs
-  cdouble *G = as_const(ps.get()->G);
-  double cur[D][NS], nxt[D][NS];
-#pragma unroll
-  for (int i = 0; i < NS; ++i) a[i] = 0.0;
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-#pragma unroll
-    for (int i = 0; i < NS; ++i) cur[d][i] = d < L ? G[d * NS + i] : 0.0;
-  }
-#pragma unroll
-  for (int jb = 0; jb < L; jb += D) {
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const int j = jb + d;
-      if (j < L) {
-        const double xd = (double)xv[j];
-        a[0] = fma(cur[d][0], xd, a[0]);
-        if (d == 0) {
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int e = 0; e < D; ++e) {
-#pragma unroll
-            for (int i = 0; i < NS; ++i) nxt[e][i] = jb + D + e < L ? G[(jb + D + e) * NS + i] : 0.0;
-          }
-          __builtin_amdgcn_sched_barrier(0);
-        }
-#pragma unroll
-        for (int i = 1; i < NS; ++i) a[i] = fma(cur[d][i], xd, a[i]);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) cur[d][i] = nxt[d][i];
-    }
-  }
+  project<K, L>(as_const(ps.get()->G), xv, a);
 }
 
 // Pass 2: DF2T recurrence of the cascade from the exact entry state z over
@@ -376,8 +332,15 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
       for (int i = 0; i < NS; ++i) z0[i] = zc[cl * NSP + i];
       mv_acc<NS>(pw, z0, a);
     }
+    // up to 4 sections the level matrix of each step is scalar-loaded (its
+    // 2K(K+1) entries fit the SGPRs), issued before the exchange so the
+    // fetch overlaps the barrier; larger cascades read it from LDS
+    constexpr bool kSgprLevels = K <= 4;
+    cdouble *Pg = as_const(ps.get()->Pw);
     int lev = 0;
     for (int d = 1; d < NB; d <<= 1, ++lev) {
+      double mt[tri_count<NS>()];
+      if constexpr (kSgprLevels) tri_load<NS>(Pg + lev * NS * NS, mt);
 #pragma unroll
       for (int i = 0; i < NS; ++i) xme[i] = a[i];
       lds_barrier();
@@ -386,7 +349,10 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
         double t[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i) t[i] = src[i];
-        mv_acc<NS>(pw + lev * NS * NS, t, a);
+        if constexpr (kSgprLevels)
+          tri_mv_acc<NS>(mt, t, a);
+        else
+          mv_acc<NS>(pw + lev * NS * NS, t, a);
       }
       lds_barrier();
     }
