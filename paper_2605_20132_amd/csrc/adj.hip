@@ -86,6 +86,7 @@ struct SlBack {
 template <int K, int L>
 __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
   constexpr int NS = 2 * K, NSP = NS + 1, NC = 5 * K;
+  constexpr bool kSgprLevels = K <= 4;
   extern __shared__ double lds[];
   aparams_t p = aparams();
   const int lane = threadIdx.x & (kWave - 1);
@@ -148,8 +149,12 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       for (int i = 0; i < NS; ++i) z0[i] = zc[cl * NSP + i];
       mv_acc<NS>(pw, z0, a);
     }
+    // level matrices scalar-loaded up to 4 sections (as in the forward kernel)
+    cdouble *Pg = as_const(aparams()->Pw);
     int lev = 0;
     for (int d = 1; d < NB; d <<= 1, ++lev) {
+      double mt[tri_count<NS>()];
+      if constexpr (kSgprLevels) tri_load<NS>(Pg + lev * NS * NS, mt);
 #pragma unroll
       for (int i = 0; i < NS; ++i) xme[i] = a[i];
       lds_barrier();
@@ -158,7 +163,10 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
         double t[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i) t[i] = src[i];
-        mv_acc<NS>(pw + lev * NS * NS, t, a);
+        if constexpr (kSgprLevels)
+          tri_mv_acc<NS>(mt, t, a);
+        else
+          mv_acc<NS>(pw + lev * NS * NS, t, a);
       }
       lds_barrier();
     }
@@ -325,8 +333,11 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       }
       __builtin_amdgcn_sched_barrier(0);
     }
+    cdouble *Pg = as_const(aparams()->Pw);
     int lev = 0;
     for (int d = 1; d < NB; d <<= 1, ++lev) {
+      double mt[tri_count<NS>()];
+      if constexpr (kSgprLevels) tri_load<NS>(Pg + lev * NS * NS, mt);
 #pragma unroll
       for (int i = 0; i < NS; ++i) xme[i] = u[i];
       lds_barrier();
@@ -335,7 +346,10 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
         double t[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i) t[i] = src[i];
-        mtv_acc<NS>(pw + lev * NS * NS, t, u);
+        if constexpr (kSgprLevels)
+          tri_mtv_acc<NS>(mt, t, u);
+        else
+          mtv_acc<NS>(pw + lev * NS * NS, t, u);
       }
       lds_barrier();
     }

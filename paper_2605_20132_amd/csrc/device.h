@@ -113,6 +113,18 @@ __device__ __forceinline__ void tri_mv_acc(const double (&m)[tri_count<NS>()], c
   }
 }
 
+// acc += M^T v with M given by tri_load.
+template <int NS>
+__device__ __forceinline__ void tri_mtv_acc(const double (&m)[tri_count<NS>()], const double (&v)[NS],
+                                            double (&acc)[NS]) {
+  int k = 0;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+#pragma unroll
+    for (int j = 0; j < (i / 2 + 1) * 2; ++j) acc[j] = fma(m[k++], v[i], acc[j]);
+  }
+}
+
 // acc += M^T v for the same M (block-upper-triangular product).
 template <int NS>
 __device__ __forceinline__ void mtv_acc(const double *M, const double (&v)[NS], double (&acc)[NS]) {
