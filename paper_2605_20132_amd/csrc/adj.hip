@@ -444,16 +444,24 @@ hipError_t launch_l(const AdjParams &p, int K, hipStream_t stream) {
   }
 }
 
-// gsos[i] += sum over groups, in group order; gpart is cleared.
-__global__ void __launch_bounds__(256) adj_reduce_kernel(double *gpart, int n_grp, int n5, double *gsos) {
-  const int i = (int)threadIdx.x;
-  if (i >= n5) return;
+// gsos[i] += sum over groups of gpart[g][i]; gpart is cleared.  Workgroup i
+// reduces column i: thread t sums groups t, t + 256, ... in order (loads
+// independent, all in flight at once), then a fixed LDS tree combines the 256
+// partial sums, so the result does not depend on timing.
+constexpr int kReduceThreads = 256;
+__global__ void __launch_bounds__(kReduceThreads) adj_reduce_kernel(double *gpart, int n_grp, int n5, double *gsos) {
+  __shared__ double part[kReduceThreads];
+  const int i = (int)blockIdx.x, t = (int)threadIdx.x;
   double s = 0.0;
-  for (int g = 0; g < n_grp; ++g) {
-    s += gpart[(size_t)g * n5 + i];
-    gpart[(size_t)g * n5 + i] = 0.0;
+  for (int g = t; g < n_grp; g += kReduceThreads) s += gpart[(size_t)g * n5 + i];
+  for (int g = t; g < n_grp; g += kReduceThreads) gpart[(size_t)g * n5 + i] = 0.0;
+  part[t] = s;
+  __syncthreads();
+  for (int h = kReduceThreads / 2; h > 0; h >>= 1) {
+    if (t < h) part[t] += part[t + h];
+    __syncthreads();
   }
-  gsos[i] += s;
+  if (t == 0) gsos[i] += part[0];
 }
 
 }  // namespace
@@ -468,7 +476,7 @@ hipError_t launch_adj(const AdjParams &p, int K, int L, hipStream_t stream) {
 
 hipError_t launch_adj_reduce(double *gpart, int n_grp, int n5, double *gsos, hipStream_t stream) {
   if (n5 < 1 || n5 > 256) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(adj_reduce_kernel, dim3(1), dim3(256), 0, stream, gpart, n_grp, n5, gsos);
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3((unsigned)n5), dim3(kReduceThreads), 0, stream, gpart, n_grp, n5, gsos);
   return hipGetLastError();
 }
 
