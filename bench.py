@@ -58,6 +58,26 @@ def measured_traffic():
     return t
 
 
+def copy_bandwidth(torch, dev, mib: int = 512, reps: int = 10) -> float:
+    """Bytes read + written per second by torch's device copy over buffers
+    rotated so that no copy finds its source in the 256 MB last-level cache."""
+    n = (mib << 20) // 4
+    bufs = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4)]
+    for b in bufs:
+        b.fill_(1.0)
+    bufs[1].copy_(bufs[0])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(reps):
+        bufs[(2 * i + 3) % 4].copy_(bufs[(2 * i + 2) % 4])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del bufs
+    return 2.0 * n * 4 / (ms / 1e3) / 1e9
+
+
 def cpu_baseline(x_dev, sos, nsta, nlta, chunk, min_seconds=10.0, max_passes=30):
     """Time the FP64 oracle (as it is) on the same record: whole passes over
     all channels in the workload's chunks, state carried, repeated until at
@@ -423,6 +443,9 @@ def main():
         log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
         del src, dst
 
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"[bench] on-box device copy {copy_gbs:.0f} GB/s (read + write)")
+
     batched = None
     if not args.no_batched:
         batched = batched_leg(F, torch, dev, 200, not args.no_parity)
@@ -436,6 +459,7 @@ def main():
     if t is not None:
         traffic = t["hbm_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "copy_peak": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "fwd_kernel<K=4,stalta,write_y>", "kernel_us": kern_ms * 1e3,
                 "kernel_us_event_pairs": pair_ms * 1e3,

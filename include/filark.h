@@ -237,10 +237,17 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
  *            them (synchronous).  Rebind when pointers or lengths change.
  *   _launch  enqueues the bound work on `stream`: a fill kernel that clears
  *            the completion stamps, then one kernel per (window round,
- *            section count), each covering every stream of that kind.  It
- *            allocates nothing and does not synchronise, so it may be
- *            captured in a HIP graph; every launch or replay advances each
- *            stream's state by its chunk, exactly like filark_sos_process.
+ *            section count), each covering every stream of that kind.  The
+ *            rounds of one section count form a chain; with more than one
+ *            section count the chains run concurrently on streams the batch
+ *            owns, forked from and joined back to `stream` by events, so the
+ *            work is ordered after earlier work on `stream` and later work
+ *            on `stream` follows it.  It allocates nothing and does not
+ *            synchronise, so it may be captured in a HIP graph (the fork and
+ *            join are captured with it); every launch or replay advances
+ *            each stream's state by its chunk, exactly like
+ *            filark_sos_process.  Launches of one batch must not overlap
+ *            (they share the side streams and the stamps).
  *   _stamps  synchronises `stream` and copies n + 1 uint64 values: the
  *            completion time of each stream's last workgroup and, last, the
  *            time the launch started, in ticks of the device's 100 MHz clock.

@@ -198,6 +198,10 @@ struct filark_batch {
   };
   std::vector<Node> nodes;
   bool bound = false;
+  // one chain of kernels per section count runs on its own stream, forked
+  // from and joined back to the caller's stream by events
+  hipStream_t side[kMaxSections] = {};
+  hipEvent_t fork = nullptr, join[kMaxSections] = {};
 };
 
 namespace {
@@ -813,9 +817,17 @@ filark_status filark_batch_create(filark_batch_t *out, int n, const filark_sos_t
   b->st.assign(states, states + n);
   b->L = t0.block;
   b->nw = t0.waves;
+  const int prev_dev = current_device();
+  if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
   hipError_t e = hipMalloc(&b->d_stamps, (size_t)(n + 1) * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemsetAsync(b->d_stamps, 0, (size_t)(n + 1) * sizeof(unsigned long long), stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int k = 0; k < kMaxSections && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
+  }
+  if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) {
     filark_batch_destroy(b);
     return fail(FILARK_EHIP, "batch allocation: %s", hipGetErrorString(e));
@@ -916,13 +928,31 @@ filark_status filark_batch_launch(filark_batch_t b, hipStream_t stream) {
   const int prev_dev = current_device();
   if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
   hipError_t e = launch_stamp_reset(b->d_stamps, (int)b->st.size(), stream);
+  // Only the window rounds of one stream depend on each other, and the
+  // streams of one section count are launched together: the chains of
+  // different section counts run concurrently on the side streams.
+  bool present[kMaxSections] = {};
+  int chains = 0;
   for (const auto &nd : b->nodes) {
-    if (e != hipSuccess) break;
-    BatchParams bp;
-    bp.descs = b->d_descs;
-    bp.items = b->d_items + nd.item_off;
-    bp.stamps = b->d_stamps;
-    e = launch_fwd_batch(bp, nd.K, b->L, nd.n_items, b->nw, nd.max_lev, stream);
+    chains += present[nd.K - 1] ? 0 : 1;
+    present[nd.K - 1] = true;
+  }
+  if (e == hipSuccess && chains > 1) e = hipEventRecord(b->fork, stream);
+  for (int K = 1; K <= kMaxSections && e == hipSuccess; ++K) {
+    if (!present[K - 1]) continue;
+    hipStream_t s = chains > 1 ? b->side[K - 1] : stream;
+    if (chains > 1) e = hipStreamWaitEvent(s, b->fork, 0);
+    for (const auto &nd : b->nodes) {  // rounds in order
+      if (e != hipSuccess) break;
+      if (nd.K != K) continue;
+      BatchParams bp;
+      bp.descs = b->d_descs;
+      bp.items = b->d_items + nd.item_off;
+      bp.stamps = b->d_stamps;
+      e = launch_fwd_batch(bp, nd.K, b->L, nd.n_items, b->nw, nd.max_lev, s);
+    }
+    if (e == hipSuccess && chains > 1) e = hipEventRecord(b->join[K - 1], s);
+    if (e == hipSuccess && chains > 1) e = hipStreamWaitEvent(stream, b->join[K - 1], 0);
   }
   if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "batch launch failed: %s", hipGetErrorString(e));
@@ -941,6 +971,11 @@ filark_status filark_batch_destroy(filark_batch_t b) {
   if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_stamps) (void)hipFree(b->d_stamps);
+  for (int k = 0; k < kMaxSections; ++k) {
+    if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
   return FILARK_OK;
 }
