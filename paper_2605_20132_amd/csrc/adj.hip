@@ -58,6 +58,15 @@ __device__ __forceinline__ double shfl_xor_d(double v, int m) {
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// 1 / v for v > 0: the hardware estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - v r), each of which squares the relative error (the plain
+// division expands to a longer sequence of scaling, fix-up and refinement).
+__device__ __forceinline__ double recip(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  r = fma(r, fma(-v, r, 1.0), r);
+  return fma(r, fma(-v, r, 1.0), r);
+}
+
 // Backward step of the STA/LTA at one row: (A, B) -> adjoints before the row,
 // (S, Lg) -> the scaled sums before the row; returns ybar of the row.
 struct SlBack {
@@ -68,7 +77,7 @@ struct SlBack {
                                          double gq, int64_t gidx) const {
     const double sta = S * cs, lta = Lg * cl;
     const bool live = gidx >= nlta && lta > 0.0;
-    const double rl = live ? 1.0 / lta : 0.0;
+    const double rl = live ? recip(lta) : 0.0;
     const double cf = sta * rl;
     const double q = live ? (mode ? 2.0 * scale * (cf - gq) : gq) : 0.0;
     const double Sb = fma(q, rl, A);
