@@ -39,14 +39,22 @@
 
 namespace filark {
 
-// Dynamic LDS of one workgroup, all FP64: filter scan exchange
-// [nw * 64][2K + 1] (the odd row pitch spreads a wave's rows over the banks),
-// STA/LTA exchange [nw * 64][2], level matrices [n_lev][2K][2K], and the
-// staged carried state of the cw channels: filter [cw][2K + 1], STA/LTA sums
-// [cw][2].
+// The scans alternate between two exchange buffers, so a step needs one
+// barrier instead of two: a wave writes the buffer of step l + 1 only after
+// the barrier of step l, which every wave reaches after its reads of step
+// l - 1, the last reads of that buffer.  The filter exchange is doubled for
+// up to 4 sections and 4 waves (three such workgroups still fit a CU's LDS);
+// the STA/LTA exchange always.
+__host__ __device__ constexpr bool fwd_double_buffer(int K, int nw) { return K <= 4 && nw <= 4; }
+
+// Dynamic LDS of one workgroup, all FP64: STA/LTA exchange [2][nw * 64][2],
+// filter scan exchange [1 or 2][nw * 64][2K + 1] (the odd row pitch spreads a
+// wave's rows over the banks), level matrices [n_lev][2K][2K], and the staged
+// carried state of the cw channels: filter [cw][2K + 1], STA/LTA sums [cw][2].
 size_t fwd_lds_bytes(int K, int nw, int n_lev, int cw) {
   const int NS = 2 * K, NSP = NS + 1;
-  return ((size_t)nw * kWave * (NSP + 2) + (size_t)n_lev * NS * NS + (size_t)cw * (NSP + 2)) *
+  const size_t n = (size_t)nw * kWave;
+  return (n * (4 + NSP * (fwd_double_buffer(K, nw) ? 2 : 1)) + (size_t)n_lev * NS * NS + (size_t)cw * (NSP + 2)) *
          sizeof(double);
 }
 
@@ -167,13 +175,17 @@ __device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, f
 
 // LDS regions of a forward workgroup (see fwd_lds_bytes).
 struct FwdLds {
+  // exchange k of a scan: xsl + k * sl_step, xch + k * ch_step (k = 0, 1)
   double *xsl, *xch, *pw, *zc, *slc;
+  int sl_step, ch_step;
   __device__ __forceinline__ FwdLds(kparams_t p, int NS) {
     extern __shared__ double lds[];
     const int NSP = NS + 1, n = p->nw * kWave;
-    xsl = lds;                        // [n][2]
-    xch = xsl + 2 * n;                // [n][NSP]
-    pw = xch + n * NSP;               // [n_lev][NS][NS]
+    xsl = lds;                        // [2][n][2]
+    sl_step = 2 * n;
+    xch = lds + 4 * n;                // [1 or 2][n][NSP]
+    ch_step = fwd_double_buffer(NS / 2, p->nw) ? n * NSP : 0;
+    pw = xch + ch_step + n * NSP;     // [n_lev][NS][NS]
     zc = pw + p->n_lev * NS * NS;     // [CW][NSP]
     slc = zc + (NSP << p->cw_log2);   // [CW][2]
   }
@@ -302,12 +314,11 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
   const int64_t c = (int64_t)g * CW + cl;
   const bool cval = c < n_ch;
   const FwdLds m(p, NS);
-  double *xsl = m.xsl;                     // [NW * 64][2] STA/LTA scan exchange
-  double *xch = m.xch;                     // [NW * 64][NSP] filter scan exchange
+
   double *pw = m.pw;                       // [n_lev][NS][NS]
   double *zc = m.zc;                       // [CW][NSP] carried state at the window start
   const double *slc = m.slc;               // [CW][2] carried STA/LTA sums
-  double *xme = xch + my * NSP;            // this lane's exchange row
+  double *xme = m.xch + my * NSP;          // this lane's row of exchange 0
 
   // the window's last row: block, wave and row within the block
   const int n_t = p->n_t;
@@ -341,11 +352,12 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
     for (int d = 1; d < NB; d <<= 1, ++lev) {
       double mt[tri_count<NS>()];
       if constexpr (kSgprLevels) tri_load<NS>(Pg + lev * NS * NS, mt);
+      double *xl = m.xch + (lev & 1) * m.ch_step + my * NSP;
 #pragma unroll
-      for (int i = 0; i < NS; ++i) xme[i] = a[i];
+      for (int i = 0; i < NS; ++i) xl[i] = a[i];
       lds_barrier();
       if (b >= d) {
-        const double *src = xme - d * CW * NSP;
+        const double *src = xl - d * CW * NSP;
         double t[NS];
 #pragma unroll
         for (int i = 0; i < NS; ++i) t[i] = src[i];
@@ -354,15 +366,17 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
         else
           mv_acc<NS>(pw + lev * NS * NS, t, a);
       }
-      lds_barrier();
+      if (m.ch_step == 0) lds_barrier();  // one exchange buffer: wait for the reads
     }
+    // the block totals, in the buffer the last step did not read
+    double *xf = m.xch + (lev & 1) * m.ch_step + my * NSP;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) xme[i] = a[i];
+    for (int i = 0; i < NS; ++i) xf[i] = a[i];
     lds_barrier();
     // entry state of the block: the state after block b - 1
     double z[NS];
     {
-      const double *src = b == 0 ? zc + cl * NSP : xme - CW * NSP;
+      const double *src = b == 0 ? zc + cl * NSP : xf - CW * NSP;
 #pragma unroll
       for (int i = 0; i < NS; ++i) z[i] = src[i];
     }
@@ -390,32 +404,33 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
       S0 = slc[cl * 2 + 0];
       L0 = slc[cl * 2 + 1];
     }
+    int lev = 0;
     {
       cdouble *dp = as_const(ps.get()->dpow);
       if (b == 0) {
         s_loc = fma(dp[0], S0, s_loc);
         l_loc = fma(dp[1], L0, l_loc);
       }
-      int lev = 0;
       for (int d = 1; d < NB; d <<= 1, ++lev) {
-        xsl[2 * my] = s_loc;
-        xsl[2 * my + 1] = l_loc;
+        double *xs = m.xsl + (lev & 1) * m.sl_step;
+        xs[2 * my] = s_loc;
+        xs[2 * my + 1] = l_loc;
         lds_barrier();
         if (b >= d) {
-          const double ts = xsl[2 * (my - d * CW)], tl = xsl[2 * (my - d * CW) + 1];
+          const double ts = xs[2 * (my - d * CW)], tl = xs[2 * (my - d * CW) + 1];
           s_loc = fma(dp[2 * lev], ts, s_loc);
           l_loc = fma(dp[2 * lev + 1], tl, l_loc);
         }
-        lds_barrier();
       }
     }
-    xsl[2 * my] = s_loc;
-    xsl[2 * my + 1] = l_loc;
+    double *xs = m.xsl + (lev & 1) * m.sl_step;
+    xs[2 * my] = s_loc;
+    xs[2 * my + 1] = l_loc;
     lds_barrier();
     double Sin = S0, Lin = L0;
     if (b > 0) {
-      Sin = xsl[2 * (my - CW)];
-      Lin = xsl[2 * (my - CW) + 1];
+      Sin = xs[2 * (my - CW)];
+      Lin = xs[2 * (my - CW) + 1];
     }
     kparams_t q = ps.get();
     if (end_lane) {
@@ -434,6 +449,24 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
   }
 }
 
+// Touch every 64-byte line of G with scalar loads (16 lines per wait) while
+// the signal loads are in flight, so pass 1's batched row fetches hit the
+// scalar cache instead of all waves of a CU missing on the same lines at once.
+template <int K, int L>
+__device__ __forceinline__ void warm_g(PSrc ps) {
+  if constexpr (K > 0) {
+    const FILARK_CONST uint32_t *Gw = (const FILARK_CONST uint32_t *)ps.get()->G;
+    constexpr int kLines = (L * 2 * K * 8 + 63) / 64, kBatch = 16;
+#pragma unroll
+    for (int b0 = 0; b0 < kLines; b0 += kBatch) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int i = b0; i < b0 + kBatch && i < kLines; ++i) acc |= Gw[i * 16];
+      asm volatile("" ::"s"(acc));
+    }
+  }
+}
+
 template <int K, int L, bool STALTA, bool WRITE_Y>
 __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   const FwdLds m(ps.get(), 2 * K);
@@ -443,6 +476,7 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   tb.read(ps);
   float xv[L];
   fwd_load<L>(ps, g, xv);
+  warm_g<K, L>(ps);
   sa.write(ps, m);
   tb.write(ps, m);
   fwd_compute<K, L, STALTA, WRITE_Y>(ps, g, xv);
