@@ -103,6 +103,14 @@ std::vector<double> matvec(const Mat &a, const std::vector<double> &v, int n) {
 struct Cascade {
   int K = 0;
   double c[kMaxSections][5];
+  // every section after the first has b0 = b2 = 1 exactly (Butterworth
+  // designs: numerators [1, +-2, 1] after the gain section)
+  bool unit_tail() const {
+    if (K < 2) return false;
+    for (int k = 1; k < K; ++k)
+      if (c[k][0] != 1.0 || c[k][2] != 1.0) return false;
+    return true;
+  }
 };
 
 // One direct-form-II-transposed step of the whole cascade.
@@ -339,7 +347,8 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
     p.n_t = (int32_t)nt;
     p.range = (int32_t)((uint64_t)nt * rowb);
     p.out_range = states_only ? 0 : p.range;
-    e = launch_fwd(p, K, t.block, sl != nullptr, !states_only && (sl == nullptr || y != nullptr), stream);
+    e = launch_fwd(p, K, t.block, sl != nullptr, !states_only && (sl == nullptr || y != nullptr),
+                   sos != nullptr && sos->cas.unit_tail(), stream);
   }
   return e;
 }

@@ -88,7 +88,7 @@ __device__ __forceinline__ void pass1(PSrc ps, const float (&xv)[L], double (&a)
 // row jcap (wave-uniform; -1 for none) the filter state is written to LDS at
 // `keep` and the sums so far are kept: in the block that holds the last row
 // of the launch, that is the carried state.
-template <int K, int L, bool STALTA, bool WRITE_Y>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT>
 __device__ __forceinline__ void pass2(PSrc ps, float (&xv)[L], double (&z)[2 * K], __amdgpu_buffer_rsrc_t ry,
                                       uint32_t vo, uint32_t rowb, double &s_loc, double &l_loc,
                                       int jcap, double *keep, double &sc, double &lc) {
@@ -109,10 +109,17 @@ __device__ __forceinline__ void pass2(PSrc ps, float (&xv)[L], double (&z)[2 * K
     double v = widen<1>(xv[j]);  // not pass 1's conversion, held until now
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      const double yk = fma(cb0[k], v, z[2 * k]);
-      z[2 * k] = fma(cna1[k], yk, fma(cb1[k], v, z[2 * k + 1]));
-      z[2 * k + 1] = fma(cna2[k], yk, cb2[k] * v);
-      v = yk;
+      if (UNIT && k > 0) {  // b0 = b2 = 1: the same values, one operation fewer
+        const double yk = v + z[2 * k];
+        z[2 * k] = fma(cna1[k], yk, fma(cb1[k], v, z[2 * k + 1]));
+        z[2 * k + 1] = fma(cna2[k], yk, v);
+        v = yk;
+      } else {
+        const double yk = fma(cb0[k], v, z[2 * k]);
+        z[2 * k] = fma(cna1[k], yk, fma(cb1[k], v, z[2 * k + 1]));
+        z[2 * k + 1] = fma(cna2[k], yk, cb2[k] * v);
+        v = yk;
+      }
     }
     const float yf = (float)v;
     xv[j] = yf;
@@ -296,7 +303,7 @@ __device__ __forceinline__ void fwd_load(PSrc ps, int g, float (&xv)[L]) {
 
 // Everything after the loads for channel group g of the stream described by
 // ps, over one window of rows: carries, passes, stores, carried state.
-template <int K, int L, bool STALTA, bool WRITE_Y>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT>
 __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
   constexpr int NS = 2 * K;
   extern __shared__ double lds[];
@@ -385,7 +392,7 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
       kparams_t q = ps.get();
       const __amdgpu_buffer_rsrc_t ry =
           rsrc(WRITE_Y ? (const void *)q->y : (const void *)q->x, WRITE_Y ? q->out_range : 0);
-      pass2<K, L, STALTA, WRITE_Y>(ps, xv, z, ry, vo, fresh(rowb), s_loc, l_loc, jcap, xme, sc, lc);
+      pass2<K, L, STALTA, WRITE_Y, UNIT>(ps, xv, z, ry, vo, fresh(rowb), s_loc, l_loc, jcap, xme, sc, lc);
     }
     if (end_lane) {  // the filter state after the last row, kept by pass 2
       double *zs = ps.get()->zs;
@@ -467,7 +474,7 @@ __device__ __forceinline__ void warm_g(PSrc ps) {
   }
 }
 
-template <int K, int L, bool STALTA, bool WRITE_Y>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT>
 __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   const FwdLds m(ps.get(), 2 * K);
   Staged<K, STALTA> sa;
@@ -479,19 +486,19 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   warm_g<K, L>(ps);
   sa.write(ps, m);
   tb.write(ps, m);
-  fwd_compute<K, L, STALTA, WRITE_Y>(ps, g, xv);
+  fwd_compute<K, L, STALTA, WRITE_Y, UNIT>(ps, g, xv);
 }
 
 // One channel group per workgroup.  Three waves per SIMD for 48- and 64-sample
 // blocks (at most 168 VGPRs), so that every workgroup of a 6000-channel chunk
 // is resident at once.
-template <int K, int L, bool STALTA, bool WRITE_Y>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT>
 __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L >= 48 ? 3 : 1)))
 fwd_kernel(FwdParams) {
   const PSrc ps{dev::kparams<FwdParams>()};
   const int g = group_of(ps.get()->per_xcd);
   if (g >= ps.get()->n_grp) return;  // whole workgroup, before any barrier
-  fwd_body<K, L, STALTA, WRITE_Y>(ps, g);
+  fwd_body<K, L, STALTA, WRITE_Y, UNIT>(ps, g);
 }
 
 // Batched launch: workgroup i runs item i of a host-built table, a channel
@@ -507,7 +514,7 @@ fwd_batch_kernel(BatchParams) {
   const int desc = it->desc;
   if (desc < 0) return;  // padding, whole workgroup
   const PSrc ps{(kparams_t)(bp->descs + desc)};
-  fwd_body<K, L, false, true>(ps, it->group);
+  fwd_body<K, L, false, true, false>(ps, it->group);
   unsigned long long *stamps = bp->stamps;
   if (stamps) {
     __syncthreads();  // every wave's stores have completed
@@ -544,35 +551,44 @@ hipError_t launch_batch_l(const BatchParams &bp, int K, int n_items, int nw, siz
   }
 }
 
-template <int K, int L, bool S, bool Y>
+template <int K, int L, bool S, bool Y, bool U>
 hipError_t launch_one(const FwdParams &p, hipStream_t stream) {
   const size_t lds = fwd_lds_bytes(K, p.nw, p.n_lev, 1 << p.cw_log2);
   const dim3 grid((unsigned)fwd_grid(p));
   const dim3 block((unsigned)(p.nw * kWave));
-  hipLaunchKernelGGL((fwd_kernel<K, L, S, Y>), grid, block, lds, stream, p);
+  hipLaunchKernelGGL((fwd_kernel<K, L, S, Y, U>), grid, block, lds, stream, p);
   return hipGetLastError();
 }
 
 template <int K, int L>
-hipError_t launch_k(const FwdParams &p, bool stalta, bool write_y, hipStream_t stream) {
-  if (K == 0) return launch_one<0, L, true, false>(p, stream);
-  if (!stalta) return launch_one<K, L, false, true>(p, stream);
-  if (write_y) return launch_one<K, L, true, true>(p, stream);
-  return launch_one<K, L, true, false>(p, stream);
+hipError_t launch_k(const FwdParams &p, bool stalta, bool write_y, bool unit, hipStream_t stream) {
+  if (K == 0) return launch_one<0, L, true, false, false>(p, stream);
+  // cascades whose later sections have b0 = b2 = 1 (every Butterworth design
+  // here) get the shorter section step; no such variant for 32-sample blocks
+  if constexpr (K >= 2 && L != 32) {
+    if (unit) {
+      if (!stalta) return launch_one<K, L, false, true, true>(p, stream);
+      if (write_y) return launch_one<K, L, true, true, true>(p, stream);
+      return launch_one<K, L, true, false, true>(p, stream);
+    }
+  }
+  if (!stalta) return launch_one<K, L, false, true, false>(p, stream);
+  if (write_y) return launch_one<K, L, true, true, false>(p, stream);
+  return launch_one<K, L, true, false, false>(p, stream);
 }
 
 template <int L>
-hipError_t launch_l(const FwdParams &p, int K, bool stalta, bool write_y, hipStream_t stream) {
+hipError_t launch_l(const FwdParams &p, int K, bool stalta, bool write_y, bool unit, hipStream_t stream) {
   switch (K) {
-    case 0: return launch_k<0, L>(p, stalta, write_y, stream);
-    case 1: return launch_k<1, L>(p, stalta, write_y, stream);
-    case 2: return launch_k<2, L>(p, stalta, write_y, stream);
-    case 3: return launch_k<3, L>(p, stalta, write_y, stream);
-    case 4: return launch_k<4, L>(p, stalta, write_y, stream);
-    case 5: return launch_k<5, L>(p, stalta, write_y, stream);
-    case 6: return launch_k<6, L>(p, stalta, write_y, stream);
-    case 7: return launch_k<7, L>(p, stalta, write_y, stream);
-    case 8: return launch_k<8, L>(p, stalta, write_y, stream);
+    case 0: return launch_k<0, L>(p, stalta, write_y, unit, stream);
+    case 1: return launch_k<1, L>(p, stalta, write_y, unit, stream);
+    case 2: return launch_k<2, L>(p, stalta, write_y, unit, stream);
+    case 3: return launch_k<3, L>(p, stalta, write_y, unit, stream);
+    case 4: return launch_k<4, L>(p, stalta, write_y, unit, stream);
+    case 5: return launch_k<5, L>(p, stalta, write_y, unit, stream);
+    case 6: return launch_k<6, L>(p, stalta, write_y, unit, stream);
+    case 7: return launch_k<7, L>(p, stalta, write_y, unit, stream);
+    case 8: return launch_k<8, L>(p, stalta, write_y, unit, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -594,12 +610,12 @@ hipError_t launch_stamp_reset(unsigned long long *stamps, int n, hipStream_t str
   return hipGetLastError();
 }
 
-hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, hipStream_t stream) {
+hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, hipStream_t stream) {
   if (p.nw < 1 || p.nw > kMaxWaves || p.n_t < 1 || p.n_lev < 1 || p.n_lev > kMaxLevels)
     return hipErrorInvalidValue;
-  if (L == 32) return launch_l<32>(p, K, stalta, write_y, stream);
-  if (L == 48) return launch_l<48>(p, K, stalta, write_y, stream);
-  if (L == 64) return launch_l<64>(p, K, stalta, write_y, stream);
+  if (L == 32) return launch_l<32>(p, K, stalta, write_y, unit, stream);
+  if (L == 48) return launch_l<48>(p, K, stalta, write_y, unit, stream);
+  if (L == 64) return launch_l<64>(p, K, stalta, write_y, unit, stream);
   return hipErrorInvalidValue;
 }
 

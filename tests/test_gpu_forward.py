@@ -129,6 +129,37 @@ def test_ragged_shapes_and_orders(F, n_ch, splits, order, btype, f1, f2, fs):
     assert max_rel_rms(cf, cfo) <= tol
 
 
+@pytest.mark.parametrize("order", [4, 8, 16])
+def test_general_numerators(F, order):
+    """Sections whose numerators are not [1, b1, 1] after the first take the
+    general section step: moving gain between sections (the same transfer
+    function) must still give the oracle's result, for every tile block."""
+    orc = _oracle()
+    sos = orc.butter_sos(order, "bandpass", 2.0, 80.0, 1000.0).copy()
+    sos[0, :3] *= 4.0
+    sos[1, :3] *= 0.25  # b0 = b2 = 0.25 in section 2
+    g = torch.Generator(device="cuda").manual_seed(77 + order)
+    n_ch, splits = 70, [600, 1, 1399]
+    x = torch.randn((sum(splits), n_ch), generator=g, device="cuda", dtype=torch.float32)
+    s = orc.Stream(sos, n_ch, 20, 200)
+    yo, cfo = s.process(x.cpu().numpy().astype(np.float64))
+    for block in (32, 48, 64):
+        st = F.SOSState(sos, n_ch)
+        sl = F.StaLtaState(20 / 1000.0, 200 / 1000.0, 1000.0, n_ch)
+        st.set_tile(block, 4, 8)
+        sl.set_tile(block, 4, 8)
+        ys, cfs, t0 = [], [], 0
+        for n in splits:
+            y, cf = F.sos_stalta_process(st, sl, x[t0:t0 + n].contiguous())
+            ys.append(y)
+            cfs.append(cf)
+            t0 += n
+        torch.cuda.synchronize()
+        st.check()
+        assert max_rel_rms(torch.cat(ys).cpu().numpy(), yo) <= tolerance_for(sos)
+        assert max_rel_rms(torch.cat(cfs).cpu().numpy(), cfo) <= tolerance_for(sos)
+
+
 @pytest.mark.parametrize("n_ch,splits", [(64, [1000, 1000, 1]), (100, [7, 700, 77])])
 def test_sos_only_and_stalta_only_entries(F, n_ch, splits):
     orc = _oracle()
