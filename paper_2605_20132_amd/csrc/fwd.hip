@@ -163,7 +163,7 @@ __device__ __forceinline__ void sums(PSrc ps, const float (&xv)[L], double &s_lo
 // Pass B: the STA/LTA sums from their exact entry values and the
 // characteristic function, stored as produced.  Rows before the warm-up
 // boundary (block row < jwarm) give zero.
-template <int L>
+template <int L, bool WARM>
 __device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, float Lf, int jwarm,
                                       __amdgpu_buffer_rsrc_t rc, uint32_t vo, uint32_t rowb) {
   kparams_t p = ps.get();
@@ -174,7 +174,7 @@ __device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, f
     Sf = fmaf(as, Sf, e);
     Lf = fmaf(al, Lf, e);
     const float r = kappa * Sf * __builtin_amdgcn_rcpf(Lf);
-    const float out = (Lf > 0.0f && j >= jwarm) ? r : 0.0f;
+    const float out = (Lf > 0.0f && (!WARM || j >= jwarm)) ? r : 0.0f;
     buf_st(rc, vo + (uint32_t)j * rowb, out);
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -452,7 +452,12 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
     const int64_t jw = q->nlta - (g0 + row0);
     const int jwarm = jw <= 0 ? 0 : (jw >= L ? L : (int)jw);
     const __amdgpu_buffer_rsrc_t rc = rsrc(q->cf ? (const void *)q->cf : (const void *)q->x, q->out_range);
-    passb<L>(ps, xv, (float)Sin, (float)Lin, jwarm, rc, vo, fresh(rowb));
+    // past the warm-up for every row of the wave (a wave-uniform test): no
+    // per-row comparison with the warm-up boundary
+    if (g0 + (int64_t)w * R * L >= q->nlta)
+      passb<L, false>(ps, xv, (float)Sin, (float)Lin, 0, rc, vo, fresh(rowb));
+    else
+      passb<L, true>(ps, xv, (float)Sin, (float)Lin, jwarm, rc, vo, fresh(rowb));
   }
 }
 
