@@ -92,7 +92,9 @@ struct SlBack {
   }
 };
 
-template <int K, int L>
+// UNIT: every section after the first has b0 = b2 = 1 (Butterworth designs),
+// so those sections skip the multiplications by them (bit-identical results).
+template <int K, int L, bool UNIT>
 __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
   constexpr int NS = 2 * K, NSP = NS + 1, NC = 5 * K;
   constexpr bool kSgprLevels = K <= 4;
@@ -197,9 +199,10 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       double v = widen<1>(xv[j]);
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const double yy = fma(coef[5 * k + 0], v, z[2 * k]);
+        const bool unit = UNIT && k > 0;
+        const double yy = unit ? v + z[2 * k] : fma(coef[5 * k + 0], v, z[2 * k]);
         z[2 * k] = fma(coef[5 * k + 3], yy, fma(coef[5 * k + 1], v, z[2 * k + 1]));
-        z[2 * k + 1] = fma(coef[5 * k + 4], yy, coef[5 * k + 2] * v);
+        z[2 * k + 1] = fma(coef[5 * k + 4], yy, unit ? v : coef[5 * k + 2] * v);
         yk[k][j] = (float)yy;
         v = yy;
       }
@@ -335,7 +338,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
         for (int k = K - 1; k >= 0; --k) {
           const double u1 = u[2 * k], u2 = u[2 * k + 1];
           const double ys = fma(coef[5 * k + 4], u2, fma(coef[5 * k + 3], u1, ybar));
-          ybar = fma(coef[5 * k + 2], u2, fma(coef[5 * k + 1], u1, coef[5 * k + 0] * ys));
+          ybar = (UNIT && k > 0) ? u2 + fma(coef[5 * k + 1], u1, ys)
+                                 : fma(coef[5 * k + 2], u2, fma(coef[5 * k + 1], u1, coef[5 * k + 0] * ys));
           u[2 * k] = ys;
           u[2 * k + 1] = u1;
         }
@@ -396,7 +400,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
           gc[5 * k + 2] = fma(u2, vin, gc[5 * k + 2]);
           gc[5 * k + 3] = fma(-u1, yout, gc[5 * k + 3]);
           gc[5 * k + 4] = fma(-u2, yout, gc[5 * k + 4]);
-          ybar = fma(coef[5 * k + 2], u2, fma(coef[5 * k + 1], u1, coef[5 * k + 0] * ys));
+          ybar = (UNIT && k > 0) ? u2 + fma(coef[5 * k + 1], u1, ys)
+                                 : fma(coef[5 * k + 2], u2, fma(coef[5 * k + 1], u1, coef[5 * k + 0] * ys));
           u[2 * k] = ys;
           u[2 * k + 1] = u1;
         }
@@ -430,25 +435,33 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
   }
 }
 
-template <int K, int L>
-hipError_t launch_one(const AdjParams &p, hipStream_t stream) {
+template <int K, int L, bool U>
+hipError_t launch_u(const AdjParams &p, hipStream_t stream) {
   const size_t lds = adj_lds_bytes(K, p.nw, p.n_lev);
-  hipLaunchKernelGGL((adj_kernel<K, L>), dim3((unsigned)grid_for(p.per_xcd)),
+  hipLaunchKernelGGL((adj_kernel<K, L, U>), dim3((unsigned)grid_for(p.per_xcd)),
                      dim3((unsigned)(p.nw * kWave)), lds, stream, p);
   return hipGetLastError();
 }
 
+template <int K, int L>
+hipError_t launch_one(const AdjParams &p, bool unit, hipStream_t stream) {
+  if constexpr (K >= 2 && L == 16) {  // the default adjoint block only
+    if (unit) return launch_u<K, L, true>(p, stream);
+  }
+  return launch_u<K, L, false>(p, stream);
+}
+
 template <int L>
-hipError_t launch_l(const AdjParams &p, int K, hipStream_t stream) {
+hipError_t launch_l(const AdjParams &p, int K, bool unit, hipStream_t stream) {
   switch (K) {
-    case 1: return launch_one<1, L>(p, stream);
-    case 2: return launch_one<2, L>(p, stream);
-    case 3: return launch_one<3, L>(p, stream);
-    case 4: return launch_one<4, L>(p, stream);
-    case 5: return launch_one<5, L>(p, stream);
-    case 6: return launch_one<6, L>(p, stream);
-    case 7: return launch_one<7, L>(p, stream);
-    case 8: return launch_one<8, L>(p, stream);
+    case 1: return launch_one<1, L>(p, unit, stream);
+    case 2: return launch_one<2, L>(p, unit, stream);
+    case 3: return launch_one<3, L>(p, unit, stream);
+    case 4: return launch_one<4, L>(p, unit, stream);
+    case 5: return launch_one<5, L>(p, unit, stream);
+    case 6: return launch_one<6, L>(p, unit, stream);
+    case 7: return launch_one<7, L>(p, unit, stream);
+    case 8: return launch_one<8, L>(p, unit, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -475,11 +488,11 @@ __global__ void __launch_bounds__(kReduceThreads) adj_reduce_kernel(double *gpar
 
 }  // namespace
 
-hipError_t launch_adj(const AdjParams &p, int K, int L, hipStream_t stream) {
+hipError_t launch_adj(const AdjParams &p, int K, int L, bool unit, hipStream_t stream) {
   if (p.nw < 1 || p.nw > kMaxWaves || p.n_t < 1 || p.n_lev < 1 || p.n_lev > kMaxLevels)
     return hipErrorInvalidValue;
-  if (L == 8) return launch_l<8>(p, K, stream);
-  if (L == 16) return launch_l<16>(p, K, stream);
+  if (L == 8) return launch_l<8>(p, K, unit, stream);
+  if (L == 16) return launch_l<16>(p, K, unit, stream);
   return hipErrorInvalidValue;
 }
 

@@ -798,7 +798,7 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
     p.zs0 = ck_z(w);
     p.sl0 = ck_s(w);
     p.cnt0 = ck_c(w);
-    e = launch_adj(p, K, ta.block, stream);
+    e = launch_adj(p, K, ta.block, sos->cas.unit_tail(), stream);
   }
   if (e == hipSuccess) e = launch_adj_reduce(sos->d_gpart, n_grp, 5 * K, gsos, stream);
   if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);

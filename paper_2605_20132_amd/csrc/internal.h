@@ -109,7 +109,7 @@ inline int fwd_grid(const FwdParams &p) { return grid_for(p.per_xcd); }
 // and the fixed-order sum of the per-group coefficient gradients into
 // gsos[5K] (added to), which also clears gpart.
 size_t adj_lds_bytes(int K, int nw, int n_lev);
-hipError_t launch_adj(const AdjParams &p, int K, int L, hipStream_t stream);
+hipError_t launch_adj(const AdjParams &p, int K, int L, bool unit, hipStream_t stream);
 hipError_t launch_adj_reduce(double *gpart, int n_grp, int n5, double *gsos, hipStream_t stream);
 
 }  // namespace filark

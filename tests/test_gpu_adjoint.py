@@ -126,6 +126,16 @@ def test_adjoint_tiles(F, tile):
     _check(*_chunk_case(F, 45, 400, 777, sos, 20, 200, 23, "mse", tile=tile))
 
 
+def test_adjoint_general_numerators(F):
+    """Gain moved between sections (same transfer function, later sections no
+    longer [1, b1, 1]): the general section step of the adjoint kernel."""
+    orc = _orc()
+    sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0).copy()
+    sos[0, :3] *= 8.0
+    sos[2, :3] *= 0.125
+    _check(*_chunk_case(F, 41, 500, 1200, sos, 20, 200, 29, "mse"))
+
+
 def test_adjoint_short_and_warmup_chunks(F):
     """Chunks shorter than one block, and chunks that straddle the warm-up."""
     orc = _orc()
