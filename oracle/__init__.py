@@ -61,6 +61,10 @@ def lib():
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         _register_grad(L)
+        L.oracle_trigger.argtypes = [ctypes.POINTER(ctypes.c_float), I64, I64, ctypes.c_float, ctypes.c_float,
+                                     ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(I64), I64,
+                                     ctypes.POINTER(I64), I64]
+        L.oracle_trigger.restype = I64
         _lib = L
     return _lib
 
@@ -211,3 +215,35 @@ def stalta_loss(sos, x, tgt, nsta: int, nlta: int, scale: float) -> float:
     y, _ = sos_filter(sos, x)
     cf, _, _ = stalta(y, nsta, nlta)
     return float(scale * np.sum((cf - _f64(tgt)) ** 2))
+
+
+class Trigger:
+    """Stateful two-threshold trigger on cf (oracle_trigger): process(cf32)
+    takes a float32 chunk [n_t, n_ch] and returns its events as int64
+    [n_events, 3] rows (channel, t_on, t_off), channel by channel in time
+    order; the open flags, open-event starts and the global sample counter
+    carry over to the next call."""
+
+    def __init__(self, n_ch: int, on: float, off: float):
+        self.n_ch = int(n_ch)
+        self.on = np.float32(on)
+        self.off = np.float32(off)
+        self.open = np.zeros(self.n_ch, dtype=np.uint8)
+        self.t_on = np.zeros(self.n_ch, dtype=np.int64)
+        self.g = 0
+
+    def process(self, cf) -> np.ndarray:
+        cf = np.ascontiguousarray(np.asarray(cf, dtype=np.float32))
+        if cf.ndim == 1:
+            cf = cf[:, None]
+        n_t, n_ch = cf.shape
+        assert n_ch == self.n_ch
+        cap = max(1, (n_t + 1) // 2 * n_ch)
+        ev = np.zeros((cap, 3), dtype=np.int64)
+        n = lib().oracle_trigger(cf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n_ch, n_t, self.on, self.off,
+                                 self.open.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                 self.t_on.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), self.g,
+                                 ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), cap)
+        assert n <= cap
+        self.g += n_t
+        return ev[:n].copy()

@@ -555,3 +555,42 @@ void oracle_sos_vjp(const double *sos, int n_sec, const double *x, const double 
     for (int i = 0; i < 5 * n_sec; ++i) gsos[i] += gch[c * 5 * n_sec + i];
   free(gch);
 }
+
+/* ------------------------------------------------------------------------
+ * Threshold trigger on a characteristic function: the monitor contract of
+ * Section 3.4 (a window of data goes in, a list of time-channel events comes
+ * out), with the classic two-threshold hysteresis of an energy detector.
+ * Per channel: while closed, the first sample whose cf exceeds `on` opens an
+ * event at that sample; while open, the first sample whose cf is below `off`
+ * closes it, and the event [t_on, t_off) is emitted.  Comparisons are made
+ * in FP32, the precision cf is delivered in.  An event still open after the
+ * last sample stays in the state (open flag and t_on), so any chunking emits
+ * the events of the one-shot run.  Sample indices are global: g0 is the
+ * index of the chunk's first sample.  Events are appended to ev[cap][3] as
+ * (channel, t_on, t_off), channel by channel in time order; the return value
+ * is the number found (events past cap are counted but not stored).
+ * ------------------------------------------------------------------------ */
+int64_t oracle_trigger(const float *cf, int64_t n_ch, int64_t n_t, float on, float off,
+                       uint8_t *open, int64_t *t_on, int64_t g0, int64_t *ev, int64_t cap) {
+  int64_t n = 0;
+  for (int64_t c = 0; c < n_ch; ++c) {
+    for (int64_t t = 0; t < n_t; ++t) {
+      const float v = cf[t * n_ch + c];
+      if (!open[c]) {
+        if (v > on) {
+          open[c] = 1;
+          t_on[c] = g0 + t;
+        }
+      } else if (v < off) {
+        if (n < cap) {
+          ev[3 * n + 0] = c;
+          ev[3 * n + 1] = t_on[c];
+          ev[3 * n + 2] = g0 + t;
+        }
+        ++n;
+        open[c] = 0;
+      }
+    }
+  }
+  return n;
+}
