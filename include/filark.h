@@ -76,6 +76,7 @@ enum { FILARK_ADJ_GRAD = 0, FILARK_ADJ_MSE = 1 };
 typedef struct filark_sos_state *filark_sos_t;
 typedef struct filark_stalta_state *filark_stalta_t;
 typedef struct filark_batch *filark_batch_t;
+typedef struct filark_trigger_state *filark_trigger_t;
 
 /*
  * Butterworth design by the bilinear transform with pre-warped band edges
@@ -260,6 +261,42 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
 filark_status filark_batch_launch(filark_batch_t b, hipStream_t stream);
 filark_status filark_batch_stamps(filark_batch_t b, uint64_t *host, hipStream_t stream);
 filark_status filark_batch_destroy(filark_batch_t b);
+
+/*
+ * Two-threshold trigger on a characteristic function: the monitor of
+ * Section 3.4 (a window of data in, a list of time-channel events out) as the
+ * hysteresis of an energy detector.  Per channel, while closed, the first
+ * sample whose cf exceeds `on` opens an event; while open, the first later
+ * sample whose cf is below `off` closes it, and the event [t_on, t_off) is
+ * emitted.  Comparisons in FP32; NaN neither opens nor closes.  An event open
+ * at the end of a call stays in the state (open flag and t_on), so any
+ * chunking emits the events of the one-shot run.  Sample indices are global
+ * (counted from the state's creation).
+ *   _init     thresholds (finite, off <= on), n_ch in [1, 2^24]; all channels
+ *             closed, counter 0.
+ *   _process  cf: device FP32 [n_t][n_ch] (e.g. the cf of
+ *             filark_sos_stalta_process); events: device int64 [cap][3]
+ *             (channel, t_on, t_off); count: device uint64, which the call
+ *             advances by the number of events that close in this chunk;
+ *             event i of the call is stored at position *count + i if that
+ *             is below cap (so a zeroed count collects several calls one
+ *             after another; events past cap are counted, not stored).  The
+ *             order of the events within a call is not specified.
+ *             Asynchronous on `stream`; n_t = 0 is a no-op.
+ *   _state_get / _set  canonical host form: open_ton [n_ch][2] int64 =
+ *             (open flag 0/1, start of the open event or 0), and the global
+ *             sample counter.  Synchronous.
+ * Errors: FILARK_EINVAL (arguments), FILARK_ESHAPE (n_ch mismatch),
+ * FILARK_EHIP.
+ */
+filark_status filark_trigger_init(filark_trigger_t *st, float on, float off, int64_t n_ch, hipStream_t stream);
+filark_status filark_trigger_process(filark_trigger_t st, const float *cf, int64_t n_ch, int64_t n_t,
+                                     int64_t *events, int64_t cap, uint64_t *count, hipStream_t stream);
+filark_status filark_trigger_state_get(filark_trigger_t st, int64_t *open_ton, int64_t *counter,
+                                       hipStream_t stream);
+filark_status filark_trigger_state_set(filark_trigger_t st, const int64_t *open_ton, int64_t counter,
+                                       hipStream_t stream);
+filark_status filark_trigger_destroy(filark_trigger_t st);
 
 /*
  * Synchronise `stream` and report an asynchronous HIP error of the work

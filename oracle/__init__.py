@@ -238,12 +238,17 @@ class Trigger:
             cf = cf[:, None]
         n_t, n_ch = cf.shape
         assert n_ch == self.n_ch
-        cap = max(1, (n_t + 1) // 2 * n_ch)
-        ev = np.zeros((cap, 3), dtype=np.int64)
-        n = lib().oracle_trigger(cf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n_ch, n_t, self.on, self.off,
-                                 self.open.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
-                                 self.t_on.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), self.g,
-                                 ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), cap)
-        assert n <= cap
+        def run(ev, cap):
+            return lib().oracle_trigger(cf.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n_ch, n_t, self.on,
+                                        self.off, self.open.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                        self.t_on.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), self.g,
+                                        ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), cap)
+
+        # count first (from a copy of the state), then store exactly that many
+        o0, t0 = self.open.copy(), self.t_on.copy()
+        n = run(np.zeros((1, 3), dtype=np.int64), 0)
+        self.open[:], self.t_on[:] = o0, t0
+        ev = np.zeros((max(1, n), 3), dtype=np.int64)
+        assert run(ev, n) == n
         self.g += n_t
         return ev[:n].copy()

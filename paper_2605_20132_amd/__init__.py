@@ -33,7 +33,8 @@ EXPORTS = (
     "filark_check", "filark_sos_destroy", "filark_stalta_destroy", "filark_last_error",
     "filark_version", "filark_tile_set", "filark_tile_get", "filark_state_bytes", "filark_state_save",
     "filark_state_load", "filark_sos_stalta_adjoint", "filark_batch_create", "filark_batch_bind",
-    "filark_batch_launch", "filark_batch_stamps", "filark_batch_destroy",
+    "filark_batch_launch", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
+    "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
 )
 
 
@@ -82,6 +83,12 @@ def lib():
     L.filark_batch_destroy.argtypes = [vp]
     L.filark_sos_destroy.argtypes = [vp]
     L.filark_stalta_destroy.argtypes = [vp]
+    I64P = ctypes.POINTER(i64)
+    L.filark_trigger_init.argtypes = [ctypes.POINTER(vp), ctypes.c_float, ctypes.c_float, i64, vp]
+    L.filark_trigger_process.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp]
+    L.filark_trigger_state_get.argtypes = [vp, I64P, I64P, vp]
+    L.filark_trigger_state_set.argtypes = [vp, I64P, i64, vp]
+    L.filark_trigger_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("filark_last_error", "filark_version"):
             getattr(L, name).restype = st
@@ -393,6 +400,59 @@ class Batch:
     def close(self):
         if self._h:
             lib().filark_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Trigger:
+    """Two-threshold trigger on cf (filark_trigger_* in include/filark.h):
+    events (channel, t_on, t_off) of the chunks passed to process(), with the
+    open events and the sample counter carried between calls."""
+
+    def __init__(self, n_ch: int, on: float, off: float, stream=None):
+        self.n_ch = int(n_ch)
+        self._h = ctypes.c_void_p()
+        _check(lib().filark_trigger_init(ctypes.byref(self._h), float(on), float(off), self.n_ch, _stream(stream)))
+
+    def process(self, cf, events, count, stream=None):
+        """cf: float32 CUDA [n_t, n_ch]; events: int64 CUDA [cap, 3]; count:
+        uint64/int64 CUDA [1], advanced by the events of this chunk (stored at
+        count + i while below cap).  Asynchronous."""
+        import torch
+
+        if cf.shape[1] != self.n_ch:
+            raise FilarkError(ESHAPE, "cf channels do not match the trigger")
+        if not (isinstance(events, torch.Tensor) and events.is_cuda and events.dtype == torch.int64
+                and events.dim() == 2 and events.shape[1] == 3 and events.is_contiguous()):
+            raise FilarkError(EINVAL, "events must be a contiguous int64 CUDA tensor [cap, 3]")
+        if not (isinstance(count, torch.Tensor) and count.is_cuda and count.numel() == 1
+                and count.element_size() == 8):
+            raise FilarkError(EINVAL, "count must be a one-element 64-bit CUDA tensor")
+        _check(lib().filark_trigger_process(self._h, _dev_f32(cf, "cf"), self.n_ch, cf.shape[0],
+                                            ctypes.c_void_p(events.data_ptr()), events.shape[0],
+                                            ctypes.c_void_p(count.data_ptr()), _stream(stream)))
+
+    def get_state(self, stream=None):
+        """(open_ton int64 [n_ch, 2] = (open flag, start of the open event), counter)."""
+        ot = np.zeros((self.n_ch, 2), dtype=np.int64)
+        g = ctypes.c_int64(0)
+        _check(lib().filark_trigger_state_get(self._h, ot.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                              ctypes.byref(g), _stream(stream)))
+        return ot, int(g.value)
+
+    def set_state(self, open_ton, counter: int, stream=None):
+        ot = np.ascontiguousarray(np.asarray(open_ton, dtype=np.int64).reshape(self.n_ch, 2))
+        _check(lib().filark_trigger_state_set(self._h, ot.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                              int(counter), _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().filark_trigger_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -212,7 +212,20 @@ struct filark_batch {
   hipEvent_t fork = nullptr, join[kMaxSections] = {};
 };
 
+struct filark_trigger_state {
+  int device = 0;
+  int64_t n_ch = 0;
+  float on = 0.f, off = 0.f;
+  int32_t *d_open = nullptr;  // [n_ch]
+  int64_t *d_ton = nullptr;   // [n_ch]
+  int64_t *d_cnt = nullptr;   // [n_ch]
+};
+
 namespace {
+
+// Trigger tile: 48-row blocks, 4 waves, groups of 8 channels (1536-row
+// windows; the kernel is compiled for 48-row blocks only).
+constexpr int kTrigBlock = 48, kTrigWaves = 4, kTrigGroup = 8;
 
 // Default adjoint tile: 16-sample blocks, 8 waves, groups of 8 channels
 // (windows of 1024 rows).
@@ -1015,6 +1028,123 @@ filark_status filark_stalta_destroy(filark_stalta_t st) {
   if (st->d_cnt) (void)hipFree(st->d_cnt);
   if (st->fwd.d) (void)hipFree(st->fwd.d);
   if (st->adj.d) (void)hipFree(st->adj.d);
+  delete st;
+  return FILARK_OK;
+}
+
+filark_status filark_trigger_init(filark_trigger_t *out, float on, float off, int64_t n_ch,
+                                  hipStream_t stream) {
+  if (!out) return fail(FILARK_EINVAL, "null trigger pointer");
+  *out = nullptr;
+  if (!std::isfinite(on) || !std::isfinite(off) || off > on)
+    return fail(FILARK_EINVAL, "thresholds must be finite with off <= on");
+  if (n_ch < 1 || n_ch > (int64_t)1 << 24) return fail(FILARK_EINVAL, "n_ch must be in [1, 2^24]");
+  filark_trigger_state *st = new (std::nothrow) filark_trigger_state();
+  if (!st) return fail(FILARK_ENOMEM, "host allocation failed");
+  st->device = current_device();
+  st->n_ch = n_ch;
+  st->on = on;
+  st->off = off;
+  hipError_t e = hipMalloc(&st->d_open, (size_t)n_ch * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemsetAsync(st->d_open, 0, (size_t)n_ch * sizeof(int32_t), stream);
+  if (e == hipSuccess) e = hipMalloc(&st->d_ton, (size_t)n_ch * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemsetAsync(st->d_ton, 0, (size_t)n_ch * sizeof(int64_t), stream);
+  if (e == hipSuccess) e = hipMalloc(&st->d_cnt, (size_t)n_ch * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemsetAsync(st->d_cnt, 0, (size_t)n_ch * sizeof(int64_t), stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    filark_trigger_destroy(st);
+    return fail(FILARK_EHIP, "trigger allocation: %s", hipGetErrorString(e));
+  }
+  *out = st;
+  return FILARK_OK;
+}
+
+filark_status filark_trigger_process(filark_trigger_t st, const float *cf, int64_t n_ch, int64_t n_t,
+                                     int64_t *events, int64_t cap, uint64_t *count, hipStream_t stream) {
+  if (!st) return fail(FILARK_EINVAL, "null trigger");
+  if (n_ch != st->n_ch) return fail(FILARK_ESHAPE, "n_ch %lld != trigger's %lld", (long long)n_ch, (long long)st->n_ch);
+  if (n_t < 0 || cap < 0) return fail(FILARK_EINVAL, "negative n_t or capacity");
+  if (!count || (cap > 0 && !events)) return fail(FILARK_EINVAL, "null count or events pointer");
+  if (n_t == 0) return FILARK_OK;
+  if (!cf) return fail(FILARK_EINVAL, "null cf pointer");
+  Tile t;
+  t.block = kTrigBlock;
+  t.waves = kTrigWaves;
+  t.group = kTrigGroup;
+  const int64_t rows = launch_rows(t, n_ch);
+  if (rows == 0) return fail(FILARK_EINVAL, "n_ch %lld too large", (long long)n_ch);
+  const int prev_dev = current_device();
+  if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));
+  TrigParams p;
+  std::memset(&p, 0, sizeof p);
+  p.n_ch = n_ch;
+  p.cw_log2 = log2_exact(t.group);
+  p.nw = t.waves;
+  p.n_grp = (int)((n_ch + t.group - 1) / t.group);
+  p.per_xcd = per_xcd_for(p.n_grp);
+  p.on = st->on;
+  p.off = st->off;
+  p.open = st->d_open;
+  p.t_on = st->d_ton;
+  p.cnt = st->d_cnt;
+  p.ev = events;
+  p.cap = cap;
+  p.count = reinterpret_cast<unsigned long long *>(count);
+  hipError_t e = hipSuccess;
+  for (int64_t t0 = 0; t0 < n_t && e == hipSuccess; t0 += rows) {
+    const int64_t nt = std::min<int64_t>(rows, n_t - t0);
+    p.cf = cf + t0 * n_ch;
+    p.n_t = (int32_t)nt;
+    p.range = (int32_t)((uint64_t)nt * (uint64_t)n_ch * 4u);
+    e = launch_trig(p, t.block, stream);
+  }
+  if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
+  if (e != hipSuccess) return fail(FILARK_EHIP, "trigger launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status filark_trigger_state_get(filark_trigger_t st, int64_t *open_ton, int64_t *counter,
+                                       hipStream_t stream) {
+  if (!st || !open_ton || !counter) return fail(FILARK_EINVAL, "null pointer");
+  HIP_TRY(hipStreamSynchronize(stream));
+  std::vector<int32_t> o((size_t)st->n_ch);
+  std::vector<int64_t> t((size_t)st->n_ch);
+  HIP_TRY(hipMemcpy(o.data(), st->d_open, o.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(t.data(), st->d_ton, t.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(counter, st->d_cnt, sizeof(int64_t), hipMemcpyDeviceToHost));
+  for (int64_t c = 0; c < st->n_ch; ++c) {
+    open_ton[2 * c] = o[c] ? 1 : 0;
+    open_ton[2 * c + 1] = o[c] ? t[c] : 0;
+  }
+  return FILARK_OK;
+}
+
+filark_status filark_trigger_state_set(filark_trigger_t st, const int64_t *open_ton, int64_t counter,
+                                       hipStream_t stream) {
+  if (!st || !open_ton) return fail(FILARK_EINVAL, "null pointer");
+  if (counter < 0) return fail(FILARK_EINVAL, "negative sample counter");
+  std::vector<int32_t> o((size_t)st->n_ch);
+  std::vector<int64_t> t((size_t)st->n_ch), g((size_t)st->n_ch, counter);
+  for (int64_t c = 0; c < st->n_ch; ++c) {
+    if (open_ton[2 * c] != 0 && open_ton[2 * c] != 1) return fail(FILARK_EINVAL, "open flag must be 0 or 1");
+    if (open_ton[2 * c] && (open_ton[2 * c + 1] < 0 || open_ton[2 * c + 1] >= counter))
+      return fail(FILARK_EINVAL, "open event must start before the counter");
+    o[c] = (int32_t)open_ton[2 * c];
+    t[c] = open_ton[2 * c + 1];
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipMemcpy(st->d_open, o.data(), o.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(st->d_ton, t.data(), t.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(st->d_cnt, g.data(), g.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  return FILARK_OK;
+}
+
+filark_status filark_trigger_destroy(filark_trigger_t st) {
+  if (!st) return FILARK_OK;
+  if (st->d_open) (void)hipFree(st->d_open);
+  if (st->d_ton) (void)hipFree(st->d_ton);
+  if (st->d_cnt) (void)hipFree(st->d_cnt);
   delete st;
   return FILARK_OK;
 }

@@ -75,6 +75,27 @@ struct AdjParams {
   int64_t nlta;
 };
 
+// Two-threshold trigger on cf (one window of a chunk).  Same work split as
+// FwdParams with 48-row blocks.  Carried per channel: open flag, start of the
+// open event (global sample index) and the global sample counter.  Events
+// closing in the window are appended to ev[cap][3] = (channel, t_on, t_off)
+// at positions reserved on *count (which counts every event, stored or not).
+struct TrigParams {
+  const float *cf;     // [n_t][n_ch]
+  int64_t n_ch;
+  int32_t n_t;         // rows in this launch (1 .. NB * 48)
+  int32_t cw_log2, nw, n_grp, per_xcd, range;
+  float on, off;
+  int32_t *open;       // [n_ch] 0 / 1, updated in place
+  int64_t *t_on;       // [n_ch], updated in place
+  int64_t *cnt;        // [n_ch] global sample index of the window start, advanced
+  int64_t *ev;         // [cap][3]
+  int64_t cap;
+  unsigned long long *count;
+};
+
+hipError_t launch_trig(const TrigParams &p, int L, hipStream_t stream);
+
 // Batched forward launch (SOS only): workgroup i runs items[i], a channel
 // group of the window described by descs[desc] (desc < 0: padding), and
 // raises stamps[stream] to its completion time.

@@ -1,0 +1,166 @@
+"""GPU parity of the two-threshold trigger against the oracle.
+
+Both sides see the same seeded synthetic FP32 cf and compare in FP32, so the
+events must be identical (integer output, bit-exact).  The order of events
+within a call is not specified on the GPU, so event lists are compared as
+sorted sets; the carried state (open flags, open-event starts, counter) must
+match exactly.  Shapes: ragged channel groups, empty and one-sample chunks,
+chunks spanning several 1536-row windows, events straddling chunk and window
+boundaries, capacity overflow, and the full 6000 x 90,000 record.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_20132_amd as F
+
+    F.lib()
+    return F
+
+
+def _orc():
+    import oracle
+
+    return oracle
+
+
+def _cf(n_t, n_ch, seed, device="cuda"):
+    """A positive process with slow swings and noise that crosses both
+    thresholds often (seeded; the same tensor feeds both sides)."""
+    g = torch.Generator(device=device).manual_seed(seed)
+    t = torch.arange(n_t, device=device, dtype=torch.float32)[:, None]
+    f = torch.rand((1, n_ch), generator=g, device=device) * 0.05 + 0.005
+    ph = torch.rand((1, n_ch), generator=g, device=device) * 6.283
+    noise = torch.randn((n_t, n_ch), generator=g, device=device) * 0.4
+    return (2.0 + 1.6 * torch.sin(f * t + ph) + noise).abs().contiguous()
+
+
+def _sorted(ev):
+    """Events as a list of tuples in (channel, t_on, t_off) order."""
+    a = np.asarray(ev, dtype=np.int64).reshape(-1, 3)
+    a = a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))]
+    return list(map(tuple, a.tolist())) if len(a) < 100_000 else a
+
+
+def _run_gpu(F, cf, splits, on, off, cap=None, count=None, tr=None):
+    n_t, n_ch = cf.shape
+    tr = tr or F.Trigger(n_ch, on, off)
+    cap = cap if cap is not None else max(1, (n_t // 2 + len(splits)) * n_ch)
+    ev = torch.full((cap, 3), -7, dtype=torch.int64, device="cuda")
+    count = count if count is not None else torch.zeros(1, dtype=torch.int64, device="cuda")
+    t0 = 0
+    for n in splits:
+        tr.process(cf[t0:t0 + n], ev, count)
+        t0 += n
+    torch.cuda.synchronize()
+    k = int(count.item())
+    return ev[:min(k, cap)].cpu().numpy(), k, tr
+
+
+def _run_oracle(cf, on, off, splits=None):
+    orc = _orc()
+    x = cf.cpu().numpy()
+    tr = orc.Trigger(x.shape[1], on, off)
+    parts, t0 = [], 0
+    for n in (splits or [x.shape[0]]):
+        parts.append(tr.process(x[t0:t0 + n]))
+        t0 += n
+    return np.concatenate(parts) if parts else np.zeros((0, 3), np.int64), tr
+
+
+@pytest.mark.parametrize("n_ch,splits", [
+    (1, [1, 2, 3, 300]),
+    (7, [5000]),
+    (9, [1536, 1, 1535, 0, 1537]),
+    (65, [100] * 30),
+    (300, [4000, 777]),
+])
+def test_events_match_oracle(F, n_ch, splits):
+    on, off = 3.0, 1.5
+    cf = _cf(sum(splits), n_ch, 11 + n_ch)
+    ev, k, tr = _run_gpu(F, cf, splits, on, off)
+    oev, otr = _run_oracle(cf, on, off, splits)
+    assert k == len(oev)
+    assert k > 0 or sum(splits) < 1000  # the longer cases cross many times
+    assert _sorted(ev) == _sorted(oev)
+    ot, g = tr.get_state()
+    assert g == otr.g == sum(splits)
+    np.testing.assert_array_equal(ot[:, 0], otr.open.astype(np.int64))
+    np.testing.assert_array_equal(ot[:, 1][otr.open == 1], otr.t_on[otr.open == 1])
+
+
+def test_chunked_equals_one_shot_on_gpu(F):
+    n_ch, on, off = 40, 3.0, 1.5
+    cf = _cf(9000, n_ch, 3)
+    a, ka, _ = _run_gpu(F, cf, [9000], on, off)
+    b, kb, _ = _run_gpu(F, cf, [1, 1499, 3000, 17, 4483], on, off)
+    assert ka == kb and _sorted(a) == _sorted(b)
+
+
+def test_capacity_overflow_and_appending_count(F):
+    n_ch, on, off = 33, 3.0, 1.5
+    cf = _cf(6000, n_ch, 5)
+    oev, _ = _run_oracle(cf, on, off)
+    total = len(oev)
+    cap = total // 3
+    ev, k, _ = _run_gpu(F, cf, [2000, 2000, 2000], on, off, cap=cap)
+    assert k == total  # every event counted
+    assert len(ev) == cap and set(_sorted(ev)) <= set(_sorted(oev))  # the stored ones are real events
+    # a count that starts at 5 appends after the first five slots
+    count = torch.full((1,), 5, dtype=torch.int64, device="cuda")
+    ev2, k2, _ = _run_gpu(F, cf, [6000], on, off, cap=total + 5, count=count)
+    assert k2 == total + 5
+    assert _sorted(ev2[5:]) == _sorted(oev)
+
+
+def test_state_set_from_oracle_and_resume(F):
+    orc = _orc()
+    n_ch, on, off = 21, 3.0, 1.5
+    cf = _cf(4000, n_ch, 9)
+    x = cf.cpu().numpy()
+    otr = orc.Trigger(n_ch, on, off)
+    otr.process(x[:2500])
+    tail_ev = otr.process(x[2500:])
+    ref = orc.Trigger(n_ch, on, off)
+    ref.process(x[:2500])
+    tr = F.Trigger(n_ch, on, off)
+    tr.set_state(np.stack([ref.open.astype(np.int64), np.where(ref.open == 1, ref.t_on, 0)], axis=1), ref.g)
+    ev, k, _ = _run_gpu(F, cf[2500:].contiguous(), [1500], on, off, tr=tr)
+    assert _sorted(ev) == _sorted(tail_ev)
+
+
+def test_argument_errors(F):
+    with pytest.raises(F.FilarkError):
+        F.Trigger(4, 1.0, 2.0)  # off > on
+    tr = F.Trigger(4, 2.0, 1.0)
+    cf = torch.zeros((10, 5), device="cuda")
+    ev = torch.zeros((4, 3), dtype=torch.int64, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    with pytest.raises(F.FilarkError) as e:
+        tr.process(cf, ev, cnt)
+    assert e.value.status == F.ESHAPE
+    with pytest.raises(F.FilarkError):
+        tr.set_state(np.array([[2, 0]] * 4), 0)  # open flag not 0/1
+
+
+def test_full_size_record(F):
+    """6000 ch x 90,000 samples in 60 chunks of 1500 (the benchmark's shape)."""
+    n_t, n_ch, chunk, on, off = 90_000, 6000, 1500, 3.0, 1.5
+    cf = _cf(n_t, n_ch, 2024)
+    cap = 6_000_000
+    ev, k, tr = _run_gpu(F, cf, [chunk] * (n_t // chunk), on, off, cap=cap)
+    oev, otr = _run_oracle(cf, on, off)
+    print(f"6000 x 90000: {k} events")
+    assert k == len(oev) <= cap
+    np.testing.assert_array_equal(_sorted(ev), _sorted(oev))
+    ot, g = tr.get_state()
+    np.testing.assert_array_equal(ot[:, 0], otr.open.astype(np.int64))
