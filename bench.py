@@ -202,6 +202,65 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
     return res
 
 
+def trigger_leg(F, torch, dev, steps: int, parity: bool):
+    """Two-threshold trigger (monitor events) on a cf-shaped record of the
+    plain-forward shape: 6000 ch x 90,000 samples in 60 chunks of 1500,
+    thresholds 3.0 / 1.5, events appended to one device buffer per step.
+    Parity: the events of 16 sampled channels against the oracle on the same
+    FP32 input (exact)."""
+    import numpy as np
+
+    import synth
+
+    n_ch, n_t, chunk, on, off = 6000, 90_000, 1500, 3.0, 1.5
+    cf = synth.cf_like(n_t, n_ch, device=dev)
+    cap = 8_000_000
+    ev = torch.empty((cap, 3), dtype=torch.int64, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    tr = F.Trigger(n_ch, on, off)
+
+    def step(t):
+        count.zero_()
+        for a in range(0, n_t, chunk):
+            t.process(cf[a:a + chunk], ev, count)
+
+    step(tr)  # warm-up (the state carries on, as for a continuing stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step(tr)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    n_ev = int(count.item())
+    res = {"workload": f"{n_ch} ch x {n_t} samples in chunks of {chunk}, thresholds {on} / {off}",
+           "ms_per_step": ms, "value": n_ch * n_t / (ms / 1e3), "unit": "channel-samples/s", "events_per_step": n_ev,
+           "algorithmic_gbs": (n_ch * n_t * 4 + n_ev * 24) / (ms / 1e3) / 1e9}
+    log(f"[bench] trigger {ms:.3f} ms/step -> {res['value']:.3e} ch-samples/s ({res['algorithmic_gbs']:.0f} GB/s, "
+        f"{n_ev} events)")
+    if parity:
+        import oracle
+
+        cols = np.random.default_rng(7).choice(n_ch, 16, replace=False)
+        t2 = F.Trigger(n_ch, on, off)
+        step(t2)
+        torch.cuda.synchronize()
+        k = int(count.item())
+        g = ev[:k].cpu().numpy()
+        x = cf[:, torch.as_tensor(cols, device=dev)].cpu().numpy()
+        o = oracle.Trigger(len(cols), on, off).process(x)
+        o[:, 0] = cols[o[:, 0]]
+        key = lambda a: a[np.lexsort((a[:, 2], a[:, 1], a[:, 0]))]
+        mine = key(g[np.isin(g[:, 0], cols)])
+        exact = bool(mine.shape == o.shape and np.array_equal(mine, key(o)))
+        res["parity"] = {"channels": len(cols), "events_compared": int(len(o)), "exact": exact}
+        log(f"[bench] trigger parity on {len(cols)} channels: {len(o)} events, exact {exact}")
+        t2.close()
+    tr.close()
+    return res
+
+
 def batched_leg(F, torch, dev, replays: int, parity: bool):
     """Batched multi-stream launch: 12 seeded streams of uneven shape (channel
     counts, rates, chunk lengths, bandpass orders drawn by
@@ -292,6 +351,7 @@ def main():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-trigger", action="store_true")
     ap.add_argument("--n-ch", type=int, default=6000)
     ap.add_argument("--n-t", type=int, default=90_000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -450,6 +510,10 @@ def main():
     if not args.no_batched:
         batched = batched_leg(F, torch, dev, 200, not args.no_parity)
 
+    trig = None
+    if not args.no_trigger:
+        trig = trigger_leg(F, torch, dev, 5, not args.no_parity)
+
     fwd_adj = None
     if not args.no_adjoint:
         fwd_adj = fwd_adjoint_leg(F, torch, dev, 3, not args.no_parity)
@@ -484,7 +548,7 @@ def main():
                                "y and cf written",
                    "io": "fp32", "filter_arith": "fp64", "stalta_arith": "fp32 block / fp64 carry"},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "graph_replay": graph,
-        "fwd_adjoint": fwd_adj, "batched": batched,
+        "fwd_adjoint": fwd_adj, "batched": batched, "trigger": trig,
     }
     print(json.dumps(out))
 

@@ -10,6 +10,7 @@ from .das import (  # noqa: F401
     Event,
     StreamSpec,
     Workload,
+    cf_like,
     draw_batched_streams,
     draw_events,
     make_config1,

@@ -207,3 +207,17 @@ def draw_batched_streams(seed: int = 20136, n_streams: int = 12) -> list[StreamS
         f2 = fs * rng.uniform(0.1, 0.4)
         out.append(StreamSpec(n_ch, fs, n_t, order, float(f1), float(f2), int(seed) * 100 + i))
     return out
+
+
+def cf_like(n_t: int, n_ch: int, seed: int = 20138, device="cpu") -> torch.Tensor:
+    """A positive FP32 series [n_t, n_ch] shaped like an STA/LTA
+    characteristic function: a slow per-channel swing 2 + 1.6 sin(f t + phase)
+    (f uniform in [0.005, 0.055] rad/sample, phase uniform) plus N(0, 0.4)
+    noise, taken in absolute value, so that thresholds such as 3.0 / 1.5 are
+    crossed often, with chattering near them."""
+    g = _gen(seed, device)
+    t = torch.arange(n_t, device=device, dtype=torch.float32)[:, None]
+    f = torch.rand((1, n_ch), generator=g, device=device) * 0.05 + 0.005
+    ph = torch.rand((1, n_ch), generator=g, device=device) * 6.283
+    noise = torch.randn((n_t, n_ch), generator=g, device=device) * 0.4
+    return (2.0 + 1.6 * torch.sin(f * t + ph) + noise).abs().contiguous()

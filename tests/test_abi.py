@@ -91,6 +91,13 @@ def test_null_and_range_errors_without_gpu(F):
     assert L.filark_sos_init(ctypes.byref(h), sos.ctypes.data_as(D), 1, 4, 7, vp(0)) == F.EINVAL
     assert L.filark_sos_init(ctypes.byref(h), sos.ctypes.data_as(D), 9, 4, 0, vp(0)) == F.EINVAL
     assert L.filark_stalta_init(ctypes.byref(h), -1.0, 1.0, 100.0, 4, vp(0)) == F.EINVAL
+    # trigger: thresholds, channel count and null handles
+    assert L.filark_trigger_init(ctypes.byref(h), 1.0, 2.0, 4, vp(0)) == F.EINVAL  # off > on
+    assert L.filark_trigger_init(ctypes.byref(h), float("nan"), 1.0, 4, vp(0)) == F.EINVAL
+    assert L.filark_trigger_init(ctypes.byref(h), 2.0, 1.0, 0, vp(0)) == F.EINVAL
+    assert L.filark_trigger_init(None, 2.0, 1.0, 4, vp(0)) == F.EINVAL
+    assert L.filark_trigger_process(vp(0), vp(0), 4, 4, vp(0), 0, vp(0), vp(0)) == F.EINVAL
+    assert L.filark_trigger_destroy(vp(0)) == F.OK
     assert L.filark_last_error()
 
 

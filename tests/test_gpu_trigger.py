@@ -33,15 +33,11 @@ def _orc():
     return oracle
 
 
-def _cf(n_t, n_ch, seed, device="cuda"):
-    """A positive process with slow swings and noise that crosses both
-    thresholds often (seeded; the same tensor feeds both sides)."""
-    g = torch.Generator(device=device).manual_seed(seed)
-    t = torch.arange(n_t, device=device, dtype=torch.float32)[:, None]
-    f = torch.rand((1, n_ch), generator=g, device=device) * 0.05 + 0.005
-    ph = torch.rand((1, n_ch), generator=g, device=device) * 6.283
-    noise = torch.randn((n_t, n_ch), generator=g, device=device) * 0.4
-    return (2.0 + 1.6 * torch.sin(f * t + ph) + noise).abs().contiguous()
+def _cf(n_t, n_ch, seed):
+    """Seeded cf-like input (synth.cf_like); the same tensor feeds both sides."""
+    import synth
+
+    return synth.cf_like(n_t, n_ch, seed, device="cuda")
 
 
 def _sorted(ev):
