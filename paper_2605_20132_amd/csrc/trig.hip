@@ -16,10 +16,12 @@
 // the map of a block applied after a prefix P is
 //   apply(S, s) = s == -1 ? S.A : (S.B == -2 ? s : S.B),
 // which composes associatively.  The blocks of a window are combined by a
-// Hillis-Steele scan in LDS, every block reruns its rows from its exact entry
-// code and counts the events that close in it, the workgroup reserves their
-// slots with one atomic add on the caller's counter, and a second rerun
-// writes them.  Rows past the end of the chunk change nothing.
+// Hillis-Steele scan in LDS.  The number of events closing in a block depends
+// only on whether it is entered open or closed, so the summary pass counts
+// both; each lane takes its slots from a workgroup counter in LDS, the
+// workgroup reserves the total with one atomic add on the caller's counter,
+// and a rerun of the block from its exact entry code writes the events.
+// Rows past the end of the chunk change nothing.
 #include "device.h"
 #include "internal.h"
 
@@ -41,7 +43,7 @@ __device__ __forceinline__ int apply(int sa, int sb, int s) {
 template <int L>
 __global__ void __launch_bounds__(kMaxWaves * kWave) trig_kernel(TrigParams) {
   __shared__ int xa[2][kMaxWaves * kWave], xb[2][kMaxWaves * kWave];  // scan exchange (double-buffered)
-  __shared__ int cnt_x[2][kMaxWaves * kWave];                         // event-count scan exchange
+  __shared__ unsigned int wg_cnt;  // events of the workgroup
   __shared__ unsigned long long base_x;
   tparams_t p = tparams();
   const int lane = threadIdx.x & (kWave - 1);
@@ -65,6 +67,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) trig_kernel(TrigParams) {
   // write-back after the scan cannot overtake them
   __shared__ int s_x[kWave];
   __shared__ int64_t ton_x[kWave], g0_x[kWave];
+  if (threadIdx.x == 0) wg_cnt = 0u;
   if (b == 0) {
     s_x[cl] = cval && p->open[c] ? -2 : -1;
     ton_x[cl] = cval ? p->t_on[c] : 0;
@@ -83,11 +86,14 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) trig_kernel(TrigParams) {
   const int s_in = s_x[cl];
   const int64_t ton_in = ton_x[cl], g0 = g0_x[cl];
 
-  // block summary: the code after the block from a closed and an open entry
-  int sa = -1, sb = -2;
+  // block summary: the code after the block from a closed and an open
+  // entry, and the events that close in it in either case
+  int sa = -1, sb = -2, ca = 0, cb = 0;
 #pragma unroll
   for (int j = 0; j < L; ++j) {
     if (j < nv) {
+      ca += (sa != -1 && xv[j] < off) ? 1 : 0;
+      cb += (sb != -1 && xv[j] < off) ? 1 : 0;
       sa = step(sa, xv[j], on, off, row0 + j);
       sb = step(sb, xv[j], on, off, row0 + j);
     }
@@ -121,38 +127,18 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) trig_kernel(TrigParams) {
     p->cnt[c] = g0 + n_t;
   }
 
-  // events closing in this block
-  int n_ev = 0;
-  {
-    int q = s;
-#pragma unroll
-    for (int j = 0; j < L; ++j) {
-      if (j < nv) {
-        n_ev += (q != -1 && xv[j] < off) ? 1 : 0;
-        q = step(q, xv[j], on, off, row0 + j);
-      }
-    }
-  }
-  if (!cval) n_ev = 0;
-
-  // exclusive prefix of the counts over the workgroup's lanes (lane order)
-  const int nthr = (int)blockDim.x;
-  int incl = n_ev;
-  lev = 0;
-  for (int d = 1; d < nthr; d <<= 1, ++lev) {
-    const int k = lev & 1;
-    cnt_x[k][threadIdx.x] = incl;
-    lds_barrier();
-    if ((int)threadIdx.x >= d) incl += cnt_x[k][threadIdx.x - d];
-  }
-  if ((int)threadIdx.x == nthr - 1) {
+  // events closing in this block, and their slots within the workgroup
+  const int n_ev = cval ? (s == -1 ? ca : cb) : 0;
+  const unsigned int mine = n_ev > 0 ? atomicAdd(&wg_cnt, (unsigned int)n_ev) : 0u;
+  __syncthreads();  // every lane's slots taken
+  if (threadIdx.x == 0) {
     // one reservation per workgroup on the caller's counter
-    base_x = incl > 0 ? atomicAdd(p->count, (unsigned long long)incl) : 0ull;
+    base_x = wg_cnt > 0u ? atomicAdd(p->count, (unsigned long long)wg_cnt) : 0ull;
   }
-  __syncthreads();  // base_x and every wave's exchange reads
+  __syncthreads();  // base_x
   if (n_ev == 0) return;
   const int64_t cap = p->cap;
-  int64_t pos = (int64_t)base_x + (incl - n_ev);
+  int64_t pos = (int64_t)base_x + (int64_t)mine;
   int64_t *ev = p->ev;
   {
     int q = s;
