@@ -65,6 +65,8 @@ def lib():
                                      ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(I64), I64,
                                      ctypes.POINTER(I64), I64]
         L.oracle_trigger.restype = I64
+        L.oracle_sos_filtfilt.argtypes = [D, ctypes.c_int, D, D, I64, I64]
+        L.oracle_sos_filtfilt.restype = None
         _lib = L
     return _lib
 
@@ -125,6 +127,18 @@ def sos_filter(sos, x, zi=None, extended: bool = False):
     f = lib().oracle_sos_filter_ld if extended else lib().oracle_sos_filter
     f(_ptr(sos), n_sec, _ptr(x), _ptr(y), n_ch, n_t, _ptr(z))
     return y, z
+
+
+def sos_filtfilt(sos, x) -> np.ndarray:
+    """Zero-phase filtering of the window x [n_t, n_ch]: the cascade forward
+    from rest, then backward in time from rest (oracle_sos_filtfilt)."""
+    sos = _f64(sos)
+    x = _f64(x)
+    if x.ndim == 1:
+        x = x[:, None]
+    y = np.empty_like(x)
+    lib().oracle_sos_filtfilt(_ptr(sos), sos.shape[0], _ptr(x), _ptr(y), x.shape[1], x.shape[0])
+    return y
 
 
 def stalta(y, nsta: int, nlta: int, st=None, g0: int = 0):

@@ -594,3 +594,39 @@ int64_t oracle_trigger(const float *cf, int64_t n_ch, int64_t n_t, float on, flo
   }
   return n;
 }
+
+/* ------------------------------------------------------------------------
+ * Zero-phase filtering of a window (the display filter's zero-phase option,
+ * Section 3.4): the cascade from rest forward over x, then from rest over the
+ * result taken backward in time; no padding at either edge.  x and y may be
+ * the same array.
+ * ------------------------------------------------------------------------ */
+static double cascade_sample(const double *sos, int n_sec, double *z, double v) {
+  for (int s = 0; s < n_sec; ++s) {
+    const double *r = sos + 6 * s;
+    const double a0 = r[3];
+    const double b0 = r[0] / a0, b1 = r[1] / a0, b2 = r[2] / a0;
+    const double a1 = r[4] / a0, a2 = r[5] / a0;
+    const double out = b0 * v + z[2 * s];
+    z[2 * s] = b1 * v - a1 * out + z[2 * s + 1];
+    z[2 * s + 1] = b2 * v - a2 * out;
+    v = out;
+  }
+  return v;
+}
+
+void oracle_sos_filtfilt(const double *sos, int n_sec, const double *x, double *y, int64_t n_ch, int64_t n_t) {
+#pragma omp parallel
+  {
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(n_t > 0 ? n_t : 1));
+    double z[2 * 64];
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < n_ch; ++c) {
+      for (int i = 0; i < 2 * n_sec; ++i) z[i] = 0.0;
+      for (int64_t t = 0; t < n_t; ++t) tmp[t] = cascade_sample(sos, n_sec, z, x[t * n_ch + c]);
+      for (int i = 0; i < 2 * n_sec; ++i) z[i] = 0.0;
+      for (int64_t t = n_t - 1; t >= 0; --t) y[t * n_ch + c] = cascade_sample(sos, n_sec, z, tmp[t]);
+    }
+    free(tmp);
+  }
+}
