@@ -135,6 +135,20 @@ filark_status filark_stalta_init(filark_stalta_t *st, double sta_s, double lta_s
                                  int64_t n_ch, hipStream_t stream);
 
 /*
+ * Zero-phase (forward-backward) SOS filtering of a window: the "zero-phase"
+ * option of the display filter of Section 3.4 (a non-causal filter of a whole
+ * window, not a stream).  The cascade runs forward over in[0 .. n_t) from
+ * rest, then backward in time over that output from rest, so the magnitude
+ * response is |H|^2 and the phase is zero; no edge padding is added.  Uses
+ * the coefficients and tile of `st` (which must have 48-sample blocks, the
+ * default); its carried state is neither read nor changed.  in / out: device FP32 [n_t][n_ch] (in == out allowed); n_ch must
+ * equal the state's and be below 2^23.  Asynchronous on `stream` (not for
+ * graph capture: it clears its work state with hipMemsetAsync).
+ */
+filark_status filark_sos_filtfilt(filark_sos_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                                  hipStream_t stream);
+
+/*
  * STA/LTA of one chunk of an already filtered signal.
  *   in  device FP32 [n_t][n_ch];  cf  device FP32 [n_t][n_ch] (may equal in).
  * Asynchronous on `stream`.

@@ -35,6 +35,7 @@ EXPORTS = (
     "filark_state_load", "filark_sos_stalta_adjoint", "filark_batch_create", "filark_batch_bind",
     "filark_batch_launch", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
     "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
+    "filark_sos_filtfilt",
 )
 
 
@@ -61,6 +62,7 @@ def lib():
                                     ctypes.c_double, D, ctypes.POINTER(ctypes.c_int)]
     L.filark_sos_init.argtypes = [ctypes.POINTER(vp), D, ctypes.c_int, i64, ctypes.c_uint, vp]
     L.filark_sos_process.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.filark_sos_filtfilt.argtypes = [vp, vp, vp, i64, i64, vp]
     L.filark_stalta_init.argtypes = [ctypes.POINTER(vp), ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      i64, vp]
     L.filark_stalta_process.argtypes = [vp, vp, vp, i64, i64, vp]
@@ -159,6 +161,17 @@ class SOSState:
             out = torch.empty_like(x)
         _check(lib().filark_sos_process(self._h, _dev_f32(x, "x"), _dev_f32(out, "out"), x.shape[1],
                                         x.shape[0], _stream(stream)))
+        return out
+
+    def filtfilt(self, x, out=None, stream=None):
+        """Zero-phase filtering of a whole window (forward, then backward in
+        time, each from rest); the carried state is not used or changed."""
+        import torch
+
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().filark_sos_filtfilt(self._h, _dev_f32(x, "x"), _dev_f32(out, "out"), x.shape[1],
+                                         x.shape[0], _stream(stream)))
         return out
 
     def get_state(self, stream=None) -> np.ndarray:

@@ -177,6 +177,8 @@ struct filark_sos_state {
   // adjoint workspace: window checkpoints and per-group coefficient sums
   double *d_ck = nullptr;
   size_t ck_bytes = 0;
+  double *d_ff = nullptr;  // zero-phase filter: the passes' own filter state
+  size_t ff_bytes = 0;
   double *d_gpart = nullptr;
   size_t gpart_bytes = 0;
 };
@@ -319,7 +321,8 @@ int64_t launch_rows(const Tile &t, int64_t n_ch) {
 // `states_only`) nothing but the state is written.
 hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_state *sl, const Tile &t,
                             double *zs, double *slst, int64_t *cnt, const float *in, float *y, float *cf,
-                            bool states_only, int64_t n_ch, int64_t n_t, hipStream_t stream) {
+                            bool states_only, int64_t n_ch, int64_t n_t, hipStream_t stream,
+                            bool rev = false) {
   const uint64_t rowb = (uint64_t)n_ch * 4u;
   const int64_t rows = launch_rows(t, n_ch);
   const int K = sos ? sos->cas.K : 0;
@@ -351,7 +354,10 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
     p.kappa = (float)((double)sl->nlta / (double)sl->nsta);
   }
   hipError_t e = hipSuccess;
-  for (int64_t t0 = 0; t0 < n_t && e == hipSuccess; t0 += rows) {
+  // time-reversed: the windows last to first, each one's rows last to first
+  const int64_t n_win = (n_t + rows - 1) / rows;
+  for (int64_t k = 0; k < n_win && e == hipSuccess; ++k) {
+    const int64_t t0 = (rev ? n_win - 1 - k : k) * rows;
     const int64_t nt = std::min(rows, n_t - t0);
     const size_t off = (size_t)t0 * (size_t)n_ch;
     p.x = in + off;
@@ -361,7 +367,7 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
     p.range = (int32_t)((uint64_t)nt * rowb);
     p.out_range = states_only ? 0 : p.range;
     e = launch_fwd(p, K, t.block, sl != nullptr, !states_only && (sl == nullptr || y != nullptr),
-                   sos != nullptr && sos->cas.unit_tail(), stream);
+                   sos != nullptr && sos->cas.unit_tail(), rev, stream);
   }
   return e;
 }
@@ -531,6 +537,42 @@ filark_status filark_sos_process(filark_sos_t st, const float *in, float *out, i
                                  int64_t n_t, hipStream_t stream) {
   if (!st) return fail(FILARK_EINVAL, "null state");
   return run_forward(st, nullptr, in, out, nullptr, n_ch, n_t, stream);
+}
+
+filark_status filark_sos_filtfilt(filark_sos_t sos, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                                  hipStream_t stream) {
+  if (!sos) return fail(FILARK_EINVAL, "null state");
+  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
+  if (n_ch != sos->n_ch)
+    return fail(FILARK_ESHAPE, "n_ch %lld differs from the SOS state's %lld", (long long)n_ch, (long long)sos->n_ch);
+  if (n_t == 0) return FILARK_OK;
+  if (!in || !out) return fail(FILARK_EINVAL, "null input or output pointer");
+  const Tile &t = sos->fwd.tile;
+  if (t.block != 48) return fail(FILARK_EINVAL, "zero-phase filtering runs on 48-sample blocks (the default tile)");
+  if (launch_rows(t, n_ch) == 0) return fail(FILARK_EINVAL, "n_ch %lld too large for the tile", (long long)n_ch);
+  const int K = sos->cas.K;
+  filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels(), t.group), t, K, sos->device);
+  if (rc != FILARK_OK) return rc;
+  const int prev_dev = current_device();
+  if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
+  const size_t bytes = (size_t)(2 * K) * (size_t)n_ch * sizeof(double);
+  rc = grow(&sos->d_ff, &sos->ff_bytes, bytes, stream);
+  hipError_t e = hipSuccess;
+  if (rc == FILARK_OK) {
+    // forward pass from rest, then the time-reversed pass over its output
+    // from rest (in place); the object's carried state is not touched
+    e = hipMemsetAsync(sos->d_ff, 0, bytes, stream);
+    if (e == hipSuccess)
+      e = forward_launches(sos, nullptr, t, sos->d_ff, nullptr, nullptr, in, out, nullptr, false, n_ch, n_t, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(sos->d_ff, 0, bytes, stream);
+    if (e == hipSuccess)
+      e = forward_launches(sos, nullptr, t, sos->d_ff, nullptr, nullptr, out, out, nullptr, false, n_ch, n_t, stream,
+                           true);
+  }
+  if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
+  if (rc != FILARK_OK) return rc;
+  if (e != hipSuccess) return fail(FILARK_EHIP, "zero-phase launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
 }
 
 filark_status filark_stalta_process(filark_stalta_t st, const float *in, float *cf, int64_t n_ch,
@@ -1017,6 +1059,7 @@ filark_status filark_sos_destroy(filark_sos_t st) {
   if (st->fwd.d) (void)hipFree(st->fwd.d);
   if (st->adj.d) (void)hipFree(st->adj.d);
   if (st->d_ck) (void)hipFree(st->d_ck);
+  if (st->d_ff) (void)hipFree(st->d_ff);
   if (st->d_gpart) (void)hipFree(st->d_gpart);
   delete st;
   return FILARK_OK;

@@ -82,15 +82,45 @@ __device__ __forceinline__ void pass1(PSrc ps, const float (&xv)[L], double (&a)
   project<K, L>(as_const(ps.get()->G), xv, a);
 }
 
+// Byte offsets of a lane's rows.  In time order row j of the lane's block is
+// at vo + j * rb (rows past the chunk and invalid channels fall past the
+// buffer range, vo >= 2^31 for the latter).  Time-reversed (REV), the
+// launch's rows are taken last to first: row row0 + j is memory row
+// n_t - 1 - row0 - j, valid while j <= jmax = n_t - 1 - row0; every other
+// row gets the out-of-range offset 2^31 explicitly, so no offset wraps.
+template <bool REV>
+struct Rows {
+  uint32_t vo, rb;
+  int jmax;
+  __device__ __forceinline__ Rows(kparams_t p, int64_t row0, int64_t c, bool cval) {
+    const uint32_t rowb = (uint32_t)p->n_ch * 4u;
+    rb = fresh(rowb);
+    if constexpr (REV) {
+      const int64_t last = (int64_t)p->n_t - 1 - row0;  // memory row of j = 0
+      jmax = cval ? (int)(last < -1 ? -1 : last) : -1;
+      vo = jmax >= 0 ? (uint32_t)((last * p->n_ch + c) * 4) : kOffInvalid;
+    } else {
+      jmax = 0;
+      vo = cval ? (uint32_t)((row0 * p->n_ch + c) * 4) : kOffInvalid;
+    }
+  }
+  __device__ __forceinline__ uint32_t off(int j) const {
+    if constexpr (REV)
+      return j <= jmax ? vo - (uint32_t)j * rb : kOffInvalid;
+    else
+      return vo + (uint32_t)j * rb;
+  }
+};
+
 // Pass 2: DF2T recurrence of the cascade from the exact entry state z over
 // the block; y replaces x in xv and is stored as produced.  With STALTA the
 // block's STA/LTA sums from zero are accumulated from the unrounded y.  After
 // row jcap (wave-uniform; -1 for none) the filter state is written to LDS at
 // `keep` and the sums so far are kept: in the block that holds the last row
 // of the launch, that is the carried state.
-template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV>
 __device__ __forceinline__ void pass2(PSrc ps, float (&xv)[L], double (&z)[2 * K], __amdgpu_buffer_rsrc_t ry,
-                                      uint32_t vo, uint32_t rowb, double &s_loc, double &l_loc,
+                                      const Rows<REV> &rw, double &s_loc, double &l_loc,
                                       int jcap, double *keep, double &sc, double &lc) {
   kparams_t p = ps.get();
   cdouble *coef = as_const(p->coef);
@@ -128,7 +158,7 @@ __device__ __forceinline__ void pass2(PSrc ps, float (&xv)[L], double (&z)[2 * K
       s_loc = fma(asd, s_loc, e);
       l_loc = fma(ald, l_loc, e);
     }
-    if constexpr (WRITE_Y) buf_st(ry, vo + (uint32_t)j * rowb, yf);
+    if constexpr (WRITE_Y) buf_st(ry, rw.off(j), yf);
     if (j == jcap) {  // a scalar branch: the side effect keeps it from being if-converted
       asm volatile("");
 #pragma unroll
@@ -165,7 +195,7 @@ __device__ __forceinline__ void sums(PSrc ps, const float (&xv)[L], double &s_lo
 // boundary (block row < jwarm) give zero.
 template <int L, bool WARM>
 __device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, float Lf, int jwarm,
-                                      __amdgpu_buffer_rsrc_t rc, uint32_t vo, uint32_t rowb) {
+                                      __amdgpu_buffer_rsrc_t rc, const Rows<false> &rw) {
   kparams_t p = ps.get();
   const float as = p->as, al = p->al, kappa = p->kappa;
 #pragma unroll
@@ -175,7 +205,7 @@ __device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, f
     Lf = fmaf(al, Lf, e);
     const float r = kappa * Sf * __builtin_amdgcn_rcpf(Lf);
     const float out = (Lf > 0.0f && (!WARM || j >= jwarm)) ? r : 0.0f;
-    buf_st(rc, vo + (uint32_t)j * rowb, out);
+    buf_st(rc, rw.off(j), out);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -277,7 +307,7 @@ struct Levels {
 };
 
 // Loads of channel group g's window into xv (issued, not waited for).
-template <int L>
+template <int L, bool REV>
 __device__ __forceinline__ void fwd_load(PSrc ps, int g, float (&xv)[L]) {
   kparams_t p = ps.get();
   const int lane = threadIdx.x & (kWave - 1);
@@ -289,21 +319,19 @@ __device__ __forceinline__ void fwd_load(PSrc ps, int g, float (&xv)[L]) {
   const int64_t n_ch = p->n_ch;
   const int64_t c = (int64_t)g * CW + cl;
   const bool cval = c < n_ch;
-  const uint32_t rowb = (uint32_t)n_ch * 4u;
   const int64_t row0 = (int64_t)b * L;
-  const uint32_t vo = cval ? (uint32_t)((row0 * n_ch + c) * 4) : kOffInvalid;
+  const Rows<REV> rw(p, row0, c, cval);
   const __amdgpu_buffer_rsrc_t rx = rsrc(ps.get()->x, ps.get()->range);
-  const uint32_t rb = fresh(rowb);
 #pragma unroll
   for (int j = 0; j < L; ++j) {
-    xv[j] = buf_ld(rx, vo + (uint32_t)j * rb);
+    xv[j] = buf_ld(rx, rw.off(j));
     if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
 // Everything after the loads for channel group g of the stream described by
 // ps, over one window of rows: carries, passes, stores, carried state.
-template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV>
 __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
   constexpr int NS = 2 * K;
   extern __shared__ double lds[];
@@ -334,9 +362,7 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
   const int jend = (n_t - 1) - b_end * L;
   const int jcap = uniform(w == w_end ? jend : -1);
   const bool end_lane = w == w_end && r == r_end && cval;
-  const uint32_t rowb = (uint32_t)n_ch * 4u;
   const int64_t row0 = (int64_t)b * L;
-  const uint32_t vo = cval ? (uint32_t)((row0 * n_ch + c) * 4) : kOffInvalid;
 
   double s_loc = 0.0, l_loc = 0.0, sc = 0.0, lc = 0.0;
   lds_barrier();  // level matrices and the staged carried state are in LDS
@@ -392,7 +418,8 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
       kparams_t q = ps.get();
       const __amdgpu_buffer_rsrc_t ry =
           rsrc(WRITE_Y ? (const void *)q->y : (const void *)q->x, WRITE_Y ? q->out_range : 0);
-      pass2<K, L, STALTA, WRITE_Y, UNIT>(ps, xv, z, ry, vo, fresh(rowb), s_loc, l_loc, jcap, xme, sc, lc);
+      const Rows<REV> rw(ps.get(), row0, c, cval);
+      pass2<K, L, STALTA, WRITE_Y, UNIT, REV>(ps, xv, z, ry, rw, s_loc, l_loc, jcap, xme, sc, lc);
     }
     if (end_lane) {  // the filter state after the last row, kept by pass 2
       double *zs = ps.get()->zs;
@@ -455,9 +482,9 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
     // past the warm-up for every row of the wave (a wave-uniform test): no
     // per-row comparison with the warm-up boundary
     if (g0 + (int64_t)w * R * L >= q->nlta)
-      passb<L, false>(ps, xv, (float)Sin, (float)Lin, 0, rc, vo, fresh(rowb));
+      passb<L, false>(ps, xv, (float)Sin, (float)Lin, 0, rc, Rows<false>(q, row0, c, cval));
     else
-      passb<L, true>(ps, xv, (float)Sin, (float)Lin, jwarm, rc, vo, fresh(rowb));
+      passb<L, true>(ps, xv, (float)Sin, (float)Lin, jwarm, rc, Rows<false>(q, row0, c, cval));
   }
 }
 
@@ -479,7 +506,7 @@ __device__ __forceinline__ void warm_g(PSrc ps) {
   }
 }
 
-template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV>
 __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   const FwdLds m(ps.get(), 2 * K);
   Staged<K, STALTA> sa;
@@ -487,23 +514,23 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   sa.read(ps, g);
   tb.read(ps);
   float xv[L];
-  fwd_load<L>(ps, g, xv);
+  fwd_load<L, REV>(ps, g, xv);
   warm_g<K, L>(ps);
   sa.write(ps, m);
   tb.write(ps, m);
-  fwd_compute<K, L, STALTA, WRITE_Y, UNIT>(ps, g, xv);
+  fwd_compute<K, L, STALTA, WRITE_Y, UNIT, REV>(ps, g, xv);
 }
 
 // One channel group per workgroup.  Three waves per SIMD for 48- and 64-sample
 // blocks (at most 168 VGPRs), so that every workgroup of a 6000-channel chunk
 // is resident at once.
-template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV>
 __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L >= 48 ? 3 : 1)))
 fwd_kernel(FwdParams) {
   const PSrc ps{dev::kparams<FwdParams>()};
   const int g = group_of(ps.get()->per_xcd);
   if (g >= ps.get()->n_grp) return;  // whole workgroup, before any barrier
-  fwd_body<K, L, STALTA, WRITE_Y, UNIT>(ps, g);
+  fwd_body<K, L, STALTA, WRITE_Y, UNIT, REV>(ps, g);
 }
 
 // Batched launch: workgroup i runs item i of a host-built table, a channel
@@ -519,7 +546,7 @@ fwd_batch_kernel(BatchParams) {
   const int desc = it->desc;
   if (desc < 0) return;  // padding, whole workgroup
   const PSrc ps{(kparams_t)(bp->descs + desc)};
-  fwd_body<K, L, false, true, false>(ps, it->group);
+  fwd_body<K, L, false, true, false, false>(ps, it->group);
   unsigned long long *stamps = bp->stamps;
   if (stamps) {
     __syncthreads();  // every wave's stores have completed
@@ -556,18 +583,28 @@ hipError_t launch_batch_l(const BatchParams &bp, int K, int n_items, int nw, siz
   }
 }
 
-template <int K, int L, bool S, bool Y, bool U>
+template <int K, int L, bool S, bool Y, bool U, bool V = false>
 hipError_t launch_one(const FwdParams &p, hipStream_t stream) {
   const size_t lds = fwd_lds_bytes(K, p.nw, p.n_lev, 1 << p.cw_log2);
   const dim3 grid((unsigned)fwd_grid(p));
   const dim3 block((unsigned)(p.nw * kWave));
-  hipLaunchKernelGGL((fwd_kernel<K, L, S, Y, U>), grid, block, lds, stream, p);
+  hipLaunchKernelGGL((fwd_kernel<K, L, S, Y, U, V>), grid, block, lds, stream, p);
   return hipGetLastError();
 }
 
 template <int K, int L>
-hipError_t launch_k(const FwdParams &p, bool stalta, bool write_y, bool unit, hipStream_t stream) {
-  if (K == 0) return launch_one<0, L, true, false, false>(p, stream);
+hipError_t launch_k(const FwdParams &p, bool stalta, bool write_y, bool unit, bool rev, hipStream_t stream) {
+  if (K == 0) return rev ? hipErrorInvalidValue : launch_one<0, L, true, false, false>(p, stream);
+  if constexpr (K >= 1 && L == 48) {
+    if (rev) {  // time-reversed: SOS only, 48-row blocks (the zero-phase filter's backward pass)
+      if (stalta || !write_y) return hipErrorInvalidValue;
+      if constexpr (K >= 2) {
+        if (unit) return launch_one<K, L, false, true, true, true>(p, stream);
+      }
+      return launch_one<K, L, false, true, false, true>(p, stream);
+    }
+  }
+  if (rev) return hipErrorInvalidValue;
   // cascades whose later sections have b0 = b2 = 1 (every Butterworth design
   // here) get the shorter section step; no such variant for 32-sample blocks
   if constexpr (K >= 2 && L != 32) {
@@ -583,17 +620,18 @@ hipError_t launch_k(const FwdParams &p, bool stalta, bool write_y, bool unit, hi
 }
 
 template <int L>
-hipError_t launch_l(const FwdParams &p, int K, bool stalta, bool write_y, bool unit, hipStream_t stream) {
+hipError_t launch_l(const FwdParams &p, int K, bool stalta, bool write_y, bool unit, bool rev,
+                    hipStream_t stream) {
   switch (K) {
-    case 0: return launch_k<0, L>(p, stalta, write_y, unit, stream);
-    case 1: return launch_k<1, L>(p, stalta, write_y, unit, stream);
-    case 2: return launch_k<2, L>(p, stalta, write_y, unit, stream);
-    case 3: return launch_k<3, L>(p, stalta, write_y, unit, stream);
-    case 4: return launch_k<4, L>(p, stalta, write_y, unit, stream);
-    case 5: return launch_k<5, L>(p, stalta, write_y, unit, stream);
-    case 6: return launch_k<6, L>(p, stalta, write_y, unit, stream);
-    case 7: return launch_k<7, L>(p, stalta, write_y, unit, stream);
-    case 8: return launch_k<8, L>(p, stalta, write_y, unit, stream);
+    case 0: return launch_k<0, L>(p, stalta, write_y, unit, rev, stream);
+    case 1: return launch_k<1, L>(p, stalta, write_y, unit, rev, stream);
+    case 2: return launch_k<2, L>(p, stalta, write_y, unit, rev, stream);
+    case 3: return launch_k<3, L>(p, stalta, write_y, unit, rev, stream);
+    case 4: return launch_k<4, L>(p, stalta, write_y, unit, rev, stream);
+    case 5: return launch_k<5, L>(p, stalta, write_y, unit, rev, stream);
+    case 6: return launch_k<6, L>(p, stalta, write_y, unit, rev, stream);
+    case 7: return launch_k<7, L>(p, stalta, write_y, unit, rev, stream);
+    case 8: return launch_k<8, L>(p, stalta, write_y, unit, rev, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -615,12 +653,13 @@ hipError_t launch_stamp_reset(unsigned long long *stamps, int n, hipStream_t str
   return hipGetLastError();
 }
 
-hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, hipStream_t stream) {
+hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, bool rev,
+                      hipStream_t stream) {
   if (p.nw < 1 || p.nw > kMaxWaves || p.n_t < 1 || p.n_lev < 1 || p.n_lev > kMaxLevels)
     return hipErrorInvalidValue;
-  if (L == 32) return launch_l<32>(p, K, stalta, write_y, unit, stream);
-  if (L == 48) return launch_l<48>(p, K, stalta, write_y, unit, stream);
-  if (L == 64) return launch_l<64>(p, K, stalta, write_y, unit, stream);
+  if (L == 32) return launch_l<32>(p, K, stalta, write_y, unit, rev, stream);
+  if (L == 48) return launch_l<48>(p, K, stalta, write_y, unit, rev, stream);
+  if (L == 64) return launch_l<64>(p, K, stalta, write_y, unit, rev, stream);
   return hipErrorInvalidValue;
 }
 

@@ -112,7 +112,8 @@ struct BatchParams {
 size_t fwd_lds_bytes(int K, int nw, int n_lev, int cw);
 
 // Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only.
-hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, hipStream_t stream);
+hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, bool rev,
+                      hipStream_t stream);
 
 // Batched launch of n_items workgroups of nw waves for K sections and
 // L-sample blocks (max_lev: the most scan levels among the descriptors), and
