@@ -202,6 +202,51 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
     return res
 
 
+def filtfilt_leg(F, torch, dev, steps: int, parity: bool):
+    """Zero-phase filtering of display windows: 6000 ch x 15,000 samples (10 s
+    at 1500 Hz) of the plain-forward record through its bandpass (8th order
+    1-100 Hz), forward then backward in time, in place.  16 B per
+    channel-sample algorithmic (x read, y written, y read, y written).
+    Parity: 16 sampled channels against the oracle."""
+    import numpy as np
+
+    import synth
+
+    w = synth.make_config2(device=dev, n_t=15_000)
+    x = w.x
+    n_t, n_ch = x.shape
+    sos = F.sos_design(w.order, w.btype, w.f1, w.f2, w.fs)
+    st = F.SOSState(sos, n_ch)
+    y = torch.empty_like(x)
+    st.filtfilt(x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        st.filtfilt(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    st.check()
+    ms = e0.elapsed_time(e1) / steps
+    res = {"workload": f"{n_ch} ch x {n_t} samples window, bandpass order {w.order} {w.f1}-{w.f2} Hz @ {w.fs} Hz",
+           "ms_per_window": ms, "value": n_ch * n_t / (ms / 1e3), "unit": "channel-samples/s",
+           "algorithmic_gbs": n_ch * n_t * 16 / (ms / 1e3) / 1e9}
+    log(f"[bench] zero-phase window {ms:.3f} ms -> {res['value']:.3e} ch-samples/s ({res['algorithmic_gbs']:.0f} GB/s)")
+    if parity:
+        import oracle
+
+        cols = np.random.default_rng(11).choice(n_ch, 16, replace=False)
+        tc = torch.as_tensor(cols, device=dev)
+        yo = oracle.sos_filtfilt(oracle.butter_sos(w.order, w.btype, w.f1, w.f2, w.fs),
+                                 x[:, tc].double().cpu().numpy())
+        yg = y[:, tc].double().cpu().numpy()
+        err = float(np.max(np.linalg.norm(yg - yo, axis=0) / np.linalg.norm(yo, axis=0)))
+        res["parity"] = {"channels": len(cols), "max_rel_rms": err, "tolerance": 1e-5}
+        log(f"[bench] zero-phase parity on {len(cols)} channels: {err:.2e}")
+    st.close()
+    return res
+
+
 def trigger_leg(F, torch, dev, steps: int, parity: bool):
     """Two-threshold trigger (monitor events) on a cf-shaped record of the
     plain-forward shape: 6000 ch x 90,000 samples in 60 chunks of 1500,
@@ -352,6 +397,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-trigger", action="store_true")
+    ap.add_argument("--no-filtfilt", action="store_true")
     ap.add_argument("--n-ch", type=int, default=6000)
     ap.add_argument("--n-t", type=int, default=90_000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -514,6 +560,10 @@ def main():
     if not args.no_trigger:
         trig = trigger_leg(F, torch, dev, 5, not args.no_parity)
 
+    ff = None
+    if not args.no_filtfilt:
+        ff = filtfilt_leg(F, torch, dev, 20, not args.no_parity)
+
     fwd_adj = None
     if not args.no_adjoint:
         fwd_adj = fwd_adjoint_leg(F, torch, dev, 3, not args.no_parity)
@@ -548,7 +598,7 @@ def main():
                                "y and cf written",
                    "io": "fp32", "filter_arith": "fp64", "stalta_arith": "fp32 block / fp64 carry"},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "graph_replay": graph,
-        "fwd_adjoint": fwd_adj, "batched": batched, "trigger": trig,
+        "fwd_adjoint": fwd_adj, "batched": batched, "trigger": trig, "zero_phase": ff,
     }
     print(json.dumps(out))
 
