@@ -67,6 +67,8 @@ def lib():
         L.oracle_trigger.restype = I64
         L.oracle_sos_filtfilt.argtypes = [D, ctypes.c_int, D, D, I64, I64]
         L.oracle_sos_filtfilt.restype = None
+        L.oracle_ema_op.argtypes = [D, D, I64, I64, I64, ctypes.c_int, D]
+        L.oracle_ema_op.restype = None
         _lib = L
     return _lib
 
@@ -266,3 +268,24 @@ class Trigger:
         assert run(ev, n) == n
         self.g += n_t
         return ev[:n].copy()
+
+
+EMA_MODES = {"demean": 0, "agc": 1}
+
+
+class Ema:
+    """Stateful running-mean removal ("demean") or running AGC ("agc") with
+    an n_win-sample exponential average (oracle_ema_op); the average carries
+    over to the next call."""
+
+    def __init__(self, n_ch: int, n_win: int, mode: str):
+        self.n_ch, self.n_win, self.mode = int(n_ch), int(n_win), EMA_MODES[mode]
+        self.avg = np.zeros(self.n_ch)
+
+    def process(self, x) -> np.ndarray:
+        x = _f64(x)
+        if x.ndim == 1:
+            x = x[:, None]
+        y = np.empty_like(x)
+        lib().oracle_ema_op(_ptr(x), _ptr(y), x.shape[1], x.shape[0], self.n_win, self.mode, _ptr(self.avg))
+        return y

@@ -630,3 +630,32 @@ void oracle_sos_filtfilt(const double *sos, int n_sec, const double *x, double *
     free(tmp);
   }
 }
+
+/* ------------------------------------------------------------------------
+ * Stateful exponential-average operators (Table 1's running mean and
+ * running AGC rows, Section 3.4): per channel, with c = 1 / n_win,
+ *   mode 0, running-mean removal:  m = (1 - c) m + c x;    y = x - m
+ *   mode 1, running AGC:           p = (1 - c) p + c x^2;  y = x / sqrt(p) (0 where p = 0)
+ * starting from the carried average avg[c] (0 at rest) and leaving the
+ * average after the last sample in it, so any chunking gives the one-shot
+ * result.  x and y may be the same array.
+ * ------------------------------------------------------------------------ */
+void oracle_ema_op(const double *x, double *y, int64_t n_ch, int64_t n_t, int64_t n_win, int mode,
+                   double *avg) {
+  const double c = 1.0 / (double)n_win;
+#pragma omp parallel for schedule(static)
+  for (int64_t ch = 0; ch < n_ch; ++ch) {
+    double a = avg[ch];
+    for (int64_t t = 0; t < n_t; ++t) {
+      const double v = x[t * n_ch + ch];
+      if (mode == 0) {
+        a = (1.0 - c) * a + c * v;
+        y[t * n_ch + ch] = v - a;
+      } else {
+        a = (1.0 - c) * a + c * v * v;
+        y[t * n_ch + ch] = a > 0.0 ? v / sqrt(a) : 0.0;
+      }
+    }
+    avg[ch] = a;
+  }
+}
