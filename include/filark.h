@@ -77,6 +77,10 @@ typedef struct filark_sos_state *filark_sos_t;
 typedef struct filark_stalta_state *filark_stalta_t;
 typedef struct filark_batch *filark_batch_t;
 typedef struct filark_trigger_state *filark_trigger_t;
+typedef struct filark_ema_state *filark_ema_t;
+
+/* Modes of filark_ema_init. */
+enum { FILARK_EMA_DEMEAN = 0, FILARK_EMA_AGC = 1 };
 
 /*
  * Butterworth design by the bilinear transform with pre-warped band edges
@@ -275,6 +279,28 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
 filark_status filark_batch_launch(filark_batch_t b, hipStream_t stream);
 filark_status filark_batch_stamps(filark_batch_t b, uint64_t *host, hipStream_t stream);
 filark_status filark_batch_destroy(filark_batch_t b);
+
+/*
+ * Stateful exponential-average operators (Table 1's running mean and running
+ * AGC rows; stateful operators of Section 3.4).  Per channel, with
+ * n_win = round(win_s * fs) and c = 1 / n_win:
+ *   FILARK_EMA_DEMEAN  m = (1 - c) m + c x;    y = x - m   (running-mean removal)
+ *   FILARK_EMA_AGC     p = (1 - c) p + c x^2;  y = x / sqrt(p), 0 where p is 0
+ *                      (or below FP32's normal range)
+ * The average is carried from call to call (0 at creation), so any chunking
+ * gives the one-shot result.
+ *   _init     mode, window (s) and rate (Hz) positive, n_ch in [1, 2^24].
+ *   _process  in / out: device FP32 [n_t][n_ch] (in == out allowed);
+ *             asynchronous on `stream`; n_t = 0 is a no-op.
+ *   _state_get / _set  the averages, host FP64 [n_ch].  Synchronous.
+ * Errors: FILARK_EINVAL, FILARK_ESHAPE (n_ch mismatch), FILARK_EHIP.
+ */
+filark_status filark_ema_init(filark_ema_t *st, int mode, double win_s, double fs, int64_t n_ch, hipStream_t stream);
+filark_status filark_ema_process(filark_ema_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                                 hipStream_t stream);
+filark_status filark_ema_state_get(filark_ema_t st, double *avg, hipStream_t stream);
+filark_status filark_ema_state_set(filark_ema_t st, const double *avg, hipStream_t stream);
+filark_status filark_ema_destroy(filark_ema_t st);
 
 /*
  * Two-threshold trigger on a characteristic function: the monitor of

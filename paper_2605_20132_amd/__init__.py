@@ -35,7 +35,8 @@ EXPORTS = (
     "filark_state_load", "filark_sos_stalta_adjoint", "filark_batch_create", "filark_batch_bind",
     "filark_batch_launch", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
     "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
-    "filark_sos_filtfilt",
+    "filark_sos_filtfilt", "filark_ema_init", "filark_ema_process", "filark_ema_state_get", "filark_ema_state_set",
+    "filark_ema_destroy",
 )
 
 
@@ -91,6 +92,11 @@ def lib():
     L.filark_trigger_state_get.argtypes = [vp, I64P, I64P, vp]
     L.filark_trigger_state_set.argtypes = [vp, I64P, i64, vp]
     L.filark_trigger_destroy.argtypes = [vp]
+    L.filark_ema_init.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_double, ctypes.c_double, i64, vp]
+    L.filark_ema_process.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.filark_ema_state_get.argtypes = [vp, D, vp]
+    L.filark_ema_state_set.argtypes = [vp, D, vp]
+    L.filark_ema_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("filark_last_error", "filark_version"):
             getattr(L, name).restype = st
@@ -466,6 +472,51 @@ class Trigger:
     def close(self):
         if self._h:
             lib().filark_trigger_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+EMA_MODES = {"demean": 0, "agc": 1}
+
+
+class Ema:
+    """Stateful running-mean removal ("demean") or running AGC ("agc") over a
+    win_s-second exponential average (filark_ema_* in include/filark.h)."""
+
+    def __init__(self, n_ch: int, win_s: float, fs: float, mode: str, stream=None):
+        self.n_ch = int(n_ch)
+        self._h = ctypes.c_void_p()
+        _check(lib().filark_ema_init(ctypes.byref(self._h), EMA_MODES[mode], float(win_s), float(fs), self.n_ch,
+                                     _stream(stream)))
+
+    def process(self, x, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().filark_ema_process(self._h, _dev_f32(x, "x"), _dev_f32(out, "out"), x.shape[1], x.shape[0],
+                                        _stream(stream)))
+        return out
+
+    def get_state(self, stream=None) -> np.ndarray:
+        buf = np.zeros(self.n_ch, dtype=np.float64)
+        _check(lib().filark_ema_state_get(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          _stream(stream)))
+        return buf
+
+    def set_state(self, avg, stream=None):
+        buf = np.ascontiguousarray(np.asarray(avg, dtype=np.float64).reshape(self.n_ch))
+        _check(lib().filark_ema_state_set(self._h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().filark_ema_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

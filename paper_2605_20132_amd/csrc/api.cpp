@@ -214,6 +214,15 @@ struct filark_batch {
   hipEvent_t fork = nullptr, join[kMaxSections] = {};
 };
 
+struct filark_ema_state {
+  int device = 0;
+  int64_t n_ch = 0, n_win = 0;
+  int mode = 0;
+  double *d_avg = nullptr;   // [n_ch]
+  double *d_tab = nullptr;   // decay powers
+  int n_lev = 0;
+};
+
 struct filark_trigger_state {
   int device = 0;
   int64_t n_ch = 0;
@@ -1071,6 +1080,113 @@ filark_status filark_stalta_destroy(filark_stalta_t st) {
   if (st->d_cnt) (void)hipFree(st->d_cnt);
   if (st->fwd.d) (void)hipFree(st->fwd.d);
   if (st->adj.d) (void)hipFree(st->adj.d);
+  delete st;
+  return FILARK_OK;
+}
+
+filark_status filark_ema_init(filark_ema_t *out, int mode, double win_s, double fs, int64_t n_ch,
+                              hipStream_t stream) {
+  if (!out) return fail(FILARK_EINVAL, "null state pointer");
+  *out = nullptr;
+  if (mode != FILARK_EMA_DEMEAN && mode != FILARK_EMA_AGC) return fail(FILARK_EINVAL, "unknown mode %d", mode);
+  if (!(fs > 0.0) || !(win_s > 0.0) || !std::isfinite(fs * win_s)) return fail(FILARK_EINVAL, "window and fs must be positive");
+  const double nw = std::round(win_s * fs);
+  if (nw < 1.0 || nw > 9.0e15) return fail(FILARK_EINVAL, "the window must round to >= 1 sample");
+  if (n_ch < 1 || n_ch > (int64_t)1 << 24) return fail(FILARK_EINVAL, "n_ch must be in [1, 2^24]");
+  filark_ema_state *st = new (std::nothrow) filark_ema_state();
+  if (!st) return fail(FILARK_ENOMEM, "host allocation failed");
+  st->device = current_device();
+  st->n_ch = n_ch;
+  st->n_win = (int64_t)nw;
+  st->mode = mode;
+  Tile t;
+  t.block = kTrigBlock;
+  t.waves = kTrigWaves;
+  t.group = kTrigGroup;
+  st->n_lev = t.levels();
+  const double a = 1.0 - 1.0 / (double)st->n_win;
+  std::vector<double> tab;
+  for (int k = 0; k < st->n_lev; ++k) tab.push_back(std::pow(a, (double)t.block * std::ldexp(1.0, k)));
+  for (int m = 0; m <= t.block; ++m) tab.push_back(std::pow(a, (double)m));
+  filark_status rc = upload(&st->d_tab, tab, stream);
+  hipError_t e = hipSuccess;
+  if (rc == FILARK_OK) {
+    e = hipMalloc(&st->d_avg, (size_t)n_ch * sizeof(double));
+    if (e == hipSuccess) e = hipMemsetAsync(st->d_avg, 0, (size_t)n_ch * sizeof(double), stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) rc = fail(FILARK_EHIP, "state allocation: %s", hipGetErrorString(e));
+  }
+  if (rc != FILARK_OK) {
+    filark_ema_destroy(st);
+    return rc;
+  }
+  *out = st;
+  return FILARK_OK;
+}
+
+filark_status filark_ema_process(filark_ema_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                                 hipStream_t stream) {
+  if (!st) return fail(FILARK_EINVAL, "null state");
+  if (n_ch != st->n_ch) return fail(FILARK_ESHAPE, "n_ch %lld != the state's %lld", (long long)n_ch, (long long)st->n_ch);
+  if (n_t < 0) return fail(FILARK_EINVAL, "negative n_t");
+  if (n_t == 0) return FILARK_OK;
+  if (!in || !out) return fail(FILARK_EINVAL, "null input or output pointer");
+  Tile t;
+  t.block = kTrigBlock;
+  t.waves = kTrigWaves;
+  t.group = kTrigGroup;
+  const int64_t rows = launch_rows(t, n_ch);
+  if (rows == 0) return fail(FILARK_EINVAL, "n_ch %lld too large", (long long)n_ch);
+  const int prev_dev = current_device();
+  if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));
+  EmaParams p;
+  std::memset(&p, 0, sizeof p);
+  p.n_ch = n_ch;
+  p.cw_log2 = log2_exact(t.group);
+  p.nw = t.waves;
+  p.n_grp = (int)((n_ch + t.group - 1) / t.group);
+  p.per_xcd = per_xcd_for(p.n_grp);
+  p.n_lev = st->n_lev;
+  p.mode = st->mode;
+  p.avg = st->d_avg;
+  p.dpow = st->d_tab;
+  p.c = 1.0 / (double)st->n_win;
+  p.a = 1.0 - p.c;
+  hipError_t e = hipSuccess;
+  for (int64_t t0 = 0; t0 < n_t && e == hipSuccess; t0 += rows) {
+    const int64_t nt = std::min<int64_t>(rows, n_t - t0);
+    p.x = in + t0 * n_ch;
+    p.y = out + t0 * n_ch;
+    p.n_t = (int32_t)nt;
+    p.range = (int32_t)((uint64_t)nt * (uint64_t)n_ch * 4u);
+    e = launch_ema(p, t.block, stream);
+  }
+  if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
+  if (e != hipSuccess) return fail(FILARK_EHIP, "launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status filark_ema_state_get(filark_ema_t st, double *avg, hipStream_t stream) {
+  if (!st || !avg) return fail(FILARK_EINVAL, "null pointer");
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipMemcpy(avg, st->d_avg, (size_t)st->n_ch * sizeof(double), hipMemcpyDeviceToHost));
+  return FILARK_OK;
+}
+
+filark_status filark_ema_state_set(filark_ema_t st, const double *avg, hipStream_t stream) {
+  if (!st || !avg) return fail(FILARK_EINVAL, "null pointer");
+  for (int64_t c = 0; c < st->n_ch; ++c)
+    if (!std::isfinite(avg[c]) || (st->mode == FILARK_EMA_AGC && avg[c] < 0.0))
+      return fail(FILARK_EINVAL, "state_set: invalid average");
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipMemcpy(st->d_avg, avg, (size_t)st->n_ch * sizeof(double), hipMemcpyHostToDevice));
+  return FILARK_OK;
+}
+
+filark_status filark_ema_destroy(filark_ema_t st) {
+  if (!st) return FILARK_OK;
+  if (st->d_avg) (void)hipFree(st->d_avg);
+  if (st->d_tab) (void)hipFree(st->d_tab);
   delete st;
   return FILARK_OK;
 }

@@ -96,6 +96,22 @@ struct TrigParams {
 
 hipError_t launch_trig(const TrigParams &p, int L, hipStream_t stream);
 
+// Stateful exponential-average operator (running-mean removal or running
+// AGC), one window of a chunk; same work split as FwdParams, 48-row blocks.
+struct EmaParams {
+  const float *x;      // [n_t][n_ch]
+  float *y;            // [n_t][n_ch] (may equal x)
+  int64_t n_ch;
+  int32_t n_t;         // rows in this launch (1 .. NB * 48)
+  int32_t cw_log2, nw, n_grp, per_xcd, n_lev, range;
+  int32_t mode;        // 0: y = x - mean; 1: y = x / sqrt(mean of x^2)
+  double *avg;         // [n_ch] carried average, updated in place
+  const double *dpow;  // [n_lev] a^(48 2^k), then [49] a^m
+  double a, c;         // decay 1 - 1/n_win and weight 1/n_win
+};
+
+hipError_t launch_ema(const EmaParams &p, int L, hipStream_t stream);
+
 // Batched forward launch (SOS only): workgroup i runs items[i], a channel
 // group of the window described by descs[desc] (desc < 0: padding), and
 // raises stamps[stream] to its completion time.
