@@ -9,6 +9,8 @@ layout ``[n_t, n_ch]``.
 
 Parity status: design, filter and STA/LTA are pinned by closed forms, brute
 force, invariants and library special cases in ``tests/test_oracle_*.py``;
+the trigger, zero-phase filtering, running averages and the FIR by closed
+forms, brute force and library special cases in their own test files;
 the gradient routines are pinned by finite differences, the transpose
 (dot-product) identity and an independent autodiff in
 ``tests/test_oracle_grad.py``.
@@ -69,6 +71,8 @@ def lib():
         L.oracle_sos_filtfilt.restype = None
         L.oracle_ema_op.argtypes = [D, D, I64, I64, I64, ctypes.c_int, D]
         L.oracle_ema_op.restype = None
+        L.oracle_fir.argtypes = [D, ctypes.c_int, D, D, I64, I64, D]
+        L.oracle_fir.restype = None
         _lib = L
     return _lib
 
@@ -288,4 +292,23 @@ class Ema:
             x = x[:, None]
         y = np.empty_like(x)
         lib().oracle_ema_op(_ptr(x), _ptr(y), x.shape[1], x.shape[0], self.n_win, self.mode, _ptr(self.avg))
+        return y
+
+
+class Fir:
+    """Realtime FIR y[t] = sum_k h[k] x[t - k] with the last M - 1 samples of
+    every channel carried between calls (oracle_fir)."""
+
+    def __init__(self, taps, n_ch: int):
+        self.h = _f64(np.asarray(taps, dtype=np.float64).ravel())
+        self.n_ch = int(n_ch)
+        self.hist = np.zeros((max(0, len(self.h) - 1), self.n_ch))
+
+    def process(self, x) -> np.ndarray:
+        x = _f64(x)
+        if x.ndim == 1:
+            x = x[:, None]
+        y = np.empty_like(x)
+        hist = self.hist if self.hist.size else np.zeros((1, self.n_ch))
+        lib().oracle_fir(_ptr(self.h), len(self.h), _ptr(x), _ptr(y), x.shape[1], x.shape[0], _ptr(hist))
         return y

@@ -16,7 +16,11 @@
  *   - bandpass / lowpass / highpass wrappers (Section 3.4), designed here as
  *     Butterworth filters by the bilinear transform with pre-warping;
  *   - a threshold energy-detector characteristic (Section 3.4, monitors),
- *     taken as the recursive STA/LTA ratio on the squared filter output.
+ *     taken as the recursive STA/LTA ratio on the squared filter output;
+ *   - the operators beside it in Table 1, each stateful across chunks:
+ *     the on/off trigger on that characteristic, zero-phase (forward-
+ *     backward) filtering of a window, running-mean removal and running AGC,
+ *     and the realtime FIR with carried history.
  * The paper gives no formula for any of these; the readings are the textbook
  * ones (Oppenheim & Schafer for the bilinear Butterworth design and the
  * direct-form-II-transposed section; the exponential recursive STA/LTA) and
@@ -657,5 +661,37 @@ void oracle_ema_op(const double *x, double *y, int64_t n_ch, int64_t n_t, int64_
       }
     }
     avg[ch] = a;
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Realtime FIR with carried history (Table 1's FIR row, Section 3.4):
+ *   y[t] = sum_{k < M} h[k] x[t - k]
+ * where samples before the chunk come from hist[M - 1][n_ch] (oldest first:
+ * hist[i] is the sample M - 1 - i before the chunk's first), zero at rest;
+ * hist is left holding the last M - 1 samples.  FP64 accumulation of the
+ * taps and samples as given.  x and y must differ.
+ * ------------------------------------------------------------------------ */
+void oracle_fir(const double *h, int M, const double *x, double *y, int64_t n_ch, int64_t n_t, double *hist) {
+  const int64_t H = M - 1;
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < n_ch; ++c) {
+    for (int64_t t = 0; t < n_t; ++t) {
+      double acc = 0.0;
+      for (int k = 0; k < M; ++k) {
+        const int64_t s = t - k;
+        const double v = s >= 0 ? x[s * n_ch + c] : hist[(H + s) * n_ch + c];
+        acc += h[k] * v;
+      }
+      y[t * n_ch + c] = acc;
+    }
+    /* the last H samples, oldest first */
+    double *tmp = (double *)malloc(sizeof(double) * (size_t)(H > 0 ? H : 1));
+    for (int64_t i = 0; i < H; ++i) {
+      const int64_t s = n_t - H + i;
+      tmp[i] = s >= 0 ? x[s * n_ch + c] : hist[(H + s) * n_ch + c];
+    }
+    for (int64_t i = 0; i < H; ++i) hist[i * n_ch + c] = tmp[i];
+    free(tmp);
   }
 }
