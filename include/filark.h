@@ -78,6 +78,7 @@ typedef struct filark_stalta_state *filark_stalta_t;
 typedef struct filark_batch *filark_batch_t;
 typedef struct filark_trigger_state *filark_trigger_t;
 typedef struct filark_ema_state *filark_ema_t;
+typedef struct filark_fir_state *filark_fir_t;
 
 /* Modes of filark_ema_init. */
 enum { FILARK_EMA_DEMEAN = 0, FILARK_EMA_AGC = 1 };
@@ -301,6 +302,40 @@ filark_status filark_ema_process(filark_ema_t st, const float *in, float *out, i
 filark_status filark_ema_state_get(filark_ema_t st, double *avg, hipStream_t stream);
 filark_status filark_ema_state_set(filark_ema_t st, const double *avg, hipStream_t stream);
 filark_status filark_ema_destroy(filark_ema_t st);
+
+/*
+ * Realtime FIR with carried history (Table 1's FIR row; a stateful operator
+ * of Section 3.4).  Per channel
+ *   y[t] = sum_{k < n_taps} h[k] x[t - k],
+ * where the n_taps - 1 samples before a chunk are the previous chunks' last
+ * samples (0 at creation), so that any chunking gives the one-shot result;
+ * on the GPU the two agree bit for bit (every output takes its taps in
+ * ascending order in FP32 FMAs).
+ *   _init      taps: host FP64 [n_taps], finite, applied as FP32;
+ *              1 <= n_taps <= 1024; n_ch in [1, 2^24] (and small enough that
+ *              (n_taps + 100) rows of n_ch floats stay below 2 GiB).
+ *   _set_tile  output rows per wave (16 or 32), waves per workgroup (1..8)
+ *              and workgroup order (0: each XCD walks along time within its
+ *              channel groups; 1: each XCD walks its rows across all channel
+ *              groups first); default 32 x 4, order 1.  Any tile gives the
+ *              same bits.
+ *   _process   in / out: device FP32 [n_t][n_ch], time-major; they must not
+ *              overlap (neighbouring outputs read the same inputs).
+ *              Asynchronous on `stream`; n_t = 0 is a no-op.  Successive
+ *              calls must be ordered (one stream, or synchronised), since
+ *              each reads the history the previous one wrote.
+ *   _state_get / _set  the history, host FP32 [n_taps - 1][n_ch], oldest row
+ *              first (nothing when n_taps = 1).  Synchronous.
+ * Errors: FILARK_EINVAL (arguments, overlap), FILARK_ESHAPE (n_ch mismatch),
+ * FILARK_EHIP.
+ */
+filark_status filark_fir_init(filark_fir_t *st, const double *taps, int n_taps, int64_t n_ch, hipStream_t stream);
+filark_status filark_fir_set_tile(filark_fir_t st, int rows, int waves, int order);
+filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                                 hipStream_t stream);
+filark_status filark_fir_state_get(filark_fir_t st, float *hist, hipStream_t stream);
+filark_status filark_fir_state_set(filark_fir_t st, const float *hist, hipStream_t stream);
+filark_status filark_fir_destroy(filark_fir_t st);
 
 /*
  * Two-threshold trigger on a characteristic function: the monitor of

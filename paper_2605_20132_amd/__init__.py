@@ -36,7 +36,8 @@ EXPORTS = (
     "filark_batch_launch", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
     "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
     "filark_sos_filtfilt", "filark_ema_init", "filark_ema_process", "filark_ema_state_get", "filark_ema_state_set",
-    "filark_ema_destroy",
+    "filark_ema_destroy", "filark_fir_init", "filark_fir_set_tile", "filark_fir_process", "filark_fir_state_get",
+    "filark_fir_state_set", "filark_fir_destroy",
 )
 
 
@@ -97,6 +98,12 @@ def lib():
     L.filark_ema_state_get.argtypes = [vp, D, vp]
     L.filark_ema_state_set.argtypes = [vp, D, vp]
     L.filark_ema_destroy.argtypes = [vp]
+    L.filark_fir_init.argtypes = [ctypes.POINTER(vp), D, ctypes.c_int, i64, vp]
+    L.filark_fir_set_tile.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.filark_fir_process.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.filark_fir_state_get.argtypes = [vp, vp, vp]
+    L.filark_fir_state_set.argtypes = [vp, vp, vp]
+    L.filark_fir_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("filark_last_error", "filark_version"):
             getattr(L, name).restype = st
@@ -517,6 +524,52 @@ class Ema:
     def close(self):
         if self._h:
             lib().filark_ema_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Fir:
+    """Realtime FIR y[t] = sum_k h[k] x[t - k] with the last len(taps) - 1
+    samples of every channel carried between calls (filark_fir_* in
+    include/filark.h).  Input and output must not overlap."""
+
+    def __init__(self, taps, n_ch: int, stream=None):
+        h = np.ascontiguousarray(np.asarray(taps, dtype=np.float64).ravel())
+        self.n_taps = int(h.size)
+        self.n_ch = int(n_ch)
+        self._h = ctypes.c_void_p()
+        _check(lib().filark_fir_init(ctypes.byref(self._h), h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     self.n_taps, self.n_ch, _stream(stream)))
+
+    def set_tile(self, rows: int, waves: int, order: int = 1):
+        _check(lib().filark_fir_set_tile(self._h, int(rows), int(waves), int(order)))
+
+    def process(self, x, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty_like(x)
+        _check(lib().filark_fir_process(self._h, _dev_f32(x, "x"), _dev_f32(out, "out"), x.shape[1], x.shape[0],
+                                        _stream(stream)))
+        return out
+
+    def get_state(self, stream=None) -> np.ndarray:
+        buf = np.zeros((max(self.n_taps - 1, 0), self.n_ch), dtype=np.float32)
+        _check(lib().filark_fir_state_get(self._h, buf.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return buf
+
+    def set_state(self, hist, stream=None):
+        buf = np.ascontiguousarray(np.asarray(hist, dtype=np.float32).reshape(max(self.n_taps - 1, 0), self.n_ch))
+        _check(lib().filark_fir_state_set(self._h, buf.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+
+    def close(self):
+        if self._h:
+            lib().filark_fir_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfilark.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.cpp", "design.cpp", "fwd.hip", "adj.hip", "trig.hip", "ema.hip"]
+SOURCES = ["api.cpp", "design.cpp", "fwd.hip", "adj.hip", "trig.hip", "ema.hip", "fir.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/filark.h"
+#include "fir.h"
 #include "internal.h"
 
 namespace filark {
@@ -221,6 +222,17 @@ struct filark_ema_state {
   double *d_avg = nullptr;   // [n_ch]
   double *d_tab = nullptr;   // decay powers
   int n_lev = 0;
+};
+
+struct filark_fir_state {
+  int device = 0;
+  int64_t n_ch = 0;
+  int n_taps = 0, n_pad = 0;      // M and M padded to the tap chunk
+  float *d_h = nullptr;           // [n_pad] FP32 taps, zero past M
+  float *d_hist[2] = {};          // [max(M - 1, 1)][n_ch] each; d_hist[cur] is current
+  int cur = 0;
+  int rows = 32, waves = 4;       // output rows per wave, waves per workgroup
+  int order = 1;                  // workgroup order: across channel groups first (whole rows per XCD)
 };
 
 struct filark_trigger_state {
@@ -1304,6 +1316,158 @@ filark_status filark_trigger_destroy(filark_trigger_t st) {
   if (st->d_open) (void)hipFree(st->d_open);
   if (st->d_ton) (void)hipFree(st->d_ton);
   if (st->d_cnt) (void)hipFree(st->d_cnt);
+  delete st;
+  return FILARK_OK;
+}
+
+namespace {
+
+// Rows per FIR launch: every byte offset the kernel forms (window rows plus
+// the taps' reach back and one wave's rows of slack) stays below 2^31.
+int64_t fir_window_rows(const filark_fir_state *st) {
+  const int64_t rowb = st->n_ch * 4;
+  const int64_t span = (int64_t)st->rows * st->waves;
+  const int64_t budget = ((int64_t)1 << 31) / rowb - (st->n_pad + st->rows + kFirChunk + 2);
+  return std::max<int64_t>(0, (budget - (st->n_pad - 1)) / span * span);
+}
+
+}  // namespace
+
+filark_status filark_fir_init(filark_fir_t *out, const double *taps, int n_taps, int64_t n_ch, hipStream_t stream) {
+  if (!out) return fail(FILARK_EINVAL, "null state pointer");
+  *out = nullptr;
+  if (!taps) return fail(FILARK_EINVAL, "null taps");
+  if (n_taps < 1 || n_taps > 1024) return fail(FILARK_EINVAL, "n_taps must be in [1, 1024]");
+  for (int k = 0; k < n_taps; ++k)
+    if (!std::isfinite(taps[k]) || std::fabs(taps[k]) > 3.0e38) return fail(FILARK_EINVAL, "taps must be finite FP32 values");
+  if (n_ch < 1 || n_ch > (int64_t)1 << 24) return fail(FILARK_EINVAL, "n_ch must be in [1, 2^24]");
+  filark_fir_state *st = new (std::nothrow) filark_fir_state();
+  if (!st) return fail(FILARK_ENOMEM, "host allocation failed");
+  st->device = current_device();
+  st->n_ch = n_ch;
+  st->n_taps = n_taps;
+  st->n_pad = (n_taps + kFirChunk - 1) / kFirChunk * kFirChunk;
+  if (fir_window_rows(st) < 1) {
+    delete st;
+    return fail(FILARK_EINVAL, "n_ch %lld too large for a %d-tap FIR", (long long)n_ch, n_taps);
+  }
+  std::vector<float> h((size_t)st->n_pad, 0.0f);
+  for (int k = 0; k < n_taps; ++k) h[k] = (float)taps[k];
+  const size_t hist_bytes = (size_t)std::max(n_taps - 1, 1) * (size_t)n_ch * sizeof(float);
+  hipError_t e = hipMalloc(&st->d_h, h.size() * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpyAsync(st->d_h, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, stream);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+    e = hipMalloc(&st->d_hist[i], hist_bytes);
+    if (e == hipSuccess) e = hipMemsetAsync(st->d_hist[i], 0, hist_bytes, stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    filark_fir_destroy(st);
+    return fail(FILARK_EHIP, "state allocation: %s", hipGetErrorString(e));
+  }
+  *out = st;
+  return FILARK_OK;
+}
+
+filark_status filark_fir_set_tile(filark_fir_t st, int rows, int waves, int order) {
+  if (!st) return fail(FILARK_EINVAL, "null state");
+  if (!fir_rows_ok(rows) || waves < 1 || waves > kMaxWaves || (order != 0 && order != 1))
+    return fail(FILARK_EINVAL, "FIR tile %dx%d order %d: rows must be 16 or 32, waves 1..%d, order 0 or 1", rows,
+                waves, order, kMaxWaves);
+  const int r0 = st->rows, w0 = st->waves;
+  st->rows = rows;
+  st->waves = waves;
+  if (fir_window_rows(st) < 1) {
+    st->rows = r0;
+    st->waves = w0;
+    return fail(FILARK_EINVAL, "FIR tile %dx%d too tall for n_ch %lld", rows, waves, (long long)st->n_ch);
+  }
+  st->order = order;
+  return FILARK_OK;
+}
+
+filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                                 hipStream_t stream) {
+  if (!st) return fail(FILARK_EINVAL, "null state");
+  if (n_ch != st->n_ch) return fail(FILARK_ESHAPE, "n_ch %lld != the state's %lld", (long long)n_ch, (long long)st->n_ch);
+  if (n_t < 0 || n_t > ((int64_t)1 << 40)) return fail(FILARK_EINVAL, "n_t out of range");
+  if (n_t == 0) return FILARK_OK;
+  if (!in || !out) return fail(FILARK_EINVAL, "null input or output pointer");
+  {
+    const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out, n = (uintptr_t)(n_t * n_ch * 4);
+    if (a < b + n && b < a + n) return fail(FILARK_EINVAL, "FIR input and output must not overlap");
+  }
+  const int64_t W = fir_window_rows(st);
+  if (W < 1) return fail(FILARK_EINVAL, "n_ch too large for this FIR tile");
+  const int prev_dev = current_device();
+  if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));
+  const int64_t rowb = n_ch * 4, hm = st->n_taps - 1, span = (int64_t)st->rows * st->waves;
+  FirParams p;
+  std::memset(&p, 0, sizeof p);
+  p.h = st->d_h;
+  p.hin = st->d_hist[st->cur];
+  p.hout = st->d_hist[st->cur ^ 1];
+  p.n_ch = n_ch;
+  p.hrange = (int32_t)(hm * rowb);
+  p.hm = (int32_t)hm;
+  p.n_chunks = st->n_pad / kFirChunk;
+  p.n_cg = (int32_t)((n_ch + kWave - 1) / kWave);
+  p.nw = st->waves;
+  p.chan_minor = st->order;
+  hipError_t e = hipSuccess;
+  for (int64_t T0 = 0; T0 < n_t && e == hipSuccess; T0 += W) {
+    const int64_t n_rows = std::min<int64_t>(W, n_t - T0);
+    const int64_t lo = std::max<int64_t>(0, T0 - (st->n_pad - 1));
+    p.x = in + lo * n_ch;
+    p.y = out + T0 * n_ch;
+    p.xoff = (int32_t)(T0 - lo);
+    p.n_rows = (int32_t)n_rows;
+    p.range = (int32_t)((T0 + n_rows - lo) * rowb);
+    p.out_range = (int32_t)(n_rows * rowb);
+    const int64_t hs = n_t - hm - T0;
+    p.hs = (int32_t)std::max<int64_t>(std::min<int64_t>(hs, n_rows), -hm);
+    p.hcopy = T0 == 0 ? (int32_t)std::max<int64_t>(0, hm - n_t) : 0;
+    p.hsrc = (int32_t)std::min<int64_t>(n_t, hm);
+    p.n_tb = (int32_t)((n_rows + span - 1) / span);
+    const int64_t n_wg = (int64_t)p.n_cg * p.n_tb;
+    if (n_wg > ((int64_t)1 << 30)) {
+      e = hipErrorInvalidValue;
+      break;
+    }
+    p.per_xcd = (int32_t)((n_wg + 7) / 8);
+    e = launch_fir(p, st->rows, stream);
+  }
+  if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
+  if (e != hipSuccess) return fail(FILARK_EHIP, "launch failed: %s", hipGetErrorString(e));
+  st->cur ^= 1;
+  return FILARK_OK;
+}
+
+filark_status filark_fir_state_get(filark_fir_t st, float *hist, hipStream_t stream) {
+  if (!st || !hist) return fail(FILARK_EINVAL, "null pointer");
+  if (st->n_taps == 1) return FILARK_OK;
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipMemcpy(hist, st->d_hist[st->cur], (size_t)(st->n_taps - 1) * st->n_ch * sizeof(float),
+                    hipMemcpyDeviceToHost));
+  return FILARK_OK;
+}
+
+filark_status filark_fir_state_set(filark_fir_t st, const float *hist, hipStream_t stream) {
+  if (!st || !hist) return fail(FILARK_EINVAL, "null pointer");
+  if (st->n_taps == 1) return FILARK_OK;
+  const size_t n = (size_t)(st->n_taps - 1) * st->n_ch;
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(hist[i])) return fail(FILARK_EINVAL, "state_set: history must be finite");
+  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(hipMemcpy(st->d_hist[st->cur], hist, n * sizeof(float), hipMemcpyHostToDevice));
+  return FILARK_OK;
+}
+
+filark_status filark_fir_destroy(filark_fir_t st) {
+  if (!st) return FILARK_OK;
+  if (st->d_h) (void)hipFree(st->d_h);
+  for (int i = 0; i < 2; ++i)
+    if (st->d_hist[i]) (void)hipFree(st->d_hist[i]);
   delete st;
   return FILARK_OK;
 }

@@ -1,0 +1,44 @@
+// Launch interface of the realtime FIR kernel (fir.hip), used by api.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace filark {
+
+// Tap chunk: taps are applied KC at a time from SGPRs; the device tap array
+// is padded with zeros to a multiple of KC.
+constexpr int kFirChunk = 32;
+
+// One launch covers a window of rows [T0, T0 + n_rows) of the chunk, in
+// workgroups of nw waves stacked in time over one group of 64 channels; each
+// wave computes R consecutive output rows of its 64 channels.  Row numbers
+// inside the kernel are relative to T0 ("window rows").
+struct FirParams {
+  const float *x;    // chunk row lo = max(0, T0 - (Mp - 1)): base of the input reads
+  float *y;          // chunk row T0
+  const float *h;    // taps [Mp], FP32, zero past the filter length
+  const float *hin;  // carried history [M - 1][n_ch], oldest row first
+  float *hout;       // history after this chunk, same layout (a different buffer)
+  int64_t n_ch;
+  int32_t xoff;       // T0 - lo: window row 0 sits xoff rows past the input base
+  int32_t n_rows;     // rows in this window
+  int32_t range;      // readable input bytes from x (through the window's end)
+  int32_t out_range;  // n_rows * n_ch * 4
+  int32_t hrange;     // (M - 1) * n_ch * 4
+  int32_t hm;         // M - 1
+  int32_t n_chunks;   // Mp / kFirChunk
+  int32_t hs;         // window row where the new history starts: n_t - (M - 1) - T0
+  int32_t hcopy;      // history rows carried over unchanged (chunks shorter than M - 1)
+  int32_t hsrc;       // first carried-over row of hin (n_t)
+  int32_t n_cg, n_tb;  // channel groups of 64, workgroups along the window's rows
+  int32_t per_xcd, nw;
+  int32_t chan_minor;  // workgroup order: 0 = along time within a channel group, 1 = across channel groups first
+};
+
+// Output rows per wave that the kernel is compiled for.
+inline bool fir_rows_ok(int R) { return R == 16 || R == 32; }
+
+hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream);
+
+}  // namespace filark

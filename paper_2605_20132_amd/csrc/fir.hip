@@ -1,0 +1,296 @@
+// Realtime FIR with carried history (Table 1's FIR row, a stateful operator
+// of Section 3.4): per channel
+//   y[t] = sum_{k < M} h[k] x[t - k],
+// where the M - 1 samples before the chunk come from the carried history,
+// which is left holding the chunk's last M - 1 samples (ping-pong buffers, so
+// the rows read and the rows written never alias).
+//
+// Direct form, one lane per channel: a wave holds 64 neighbouring channels
+// (one 256-byte segment of every row) and R consecutive output rows in FP32
+// accumulators.  Taps are applied 32 at a time from SGPRs (one scalar fetch
+// per wave); for each tap chunk the lane loads the R + 31 input rows that the
+// chunk touches and does R x 32 FMAs.  Every output takes its taps in
+// ascending order, whatever the chunking, so a chunked run equals the one-shot
+// run bit for bit.  The kernel is bound by FMA issue at long filters and by
+// HBM at short ones; halo rows that neighbouring waves share are re-read from
+// L1/L2, not HBM.  By default each XCD walks its rows across all channel
+// groups before moving on in time, so the XCD streams whole rows, and the
+// halo of a row block was read by the same XCD one sweep earlier.  Up to 64
+// taps a second, unrolled kernel loads each input row once per wave.
+#include "device.h"
+#include "fir.h"
+
+namespace filark {
+namespace {
+
+using namespace dev;
+typedef const FILARK_CONST float cfloat;
+typedef const FILARK_CONST FirParams *firparams_t;
+__device__ __forceinline__ firparams_t firparams() { return dev::kparams<FirParams>(); }
+
+template <int R>
+__global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
+  constexpr int KC = kFirChunk;
+  constexpr int NX = R + KC - 1;  // input rows one tap chunk touches
+  firparams_t p = firparams();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = uniform(threadIdx.x / kWave);
+  const int g = group_of(p->per_xcd);
+  const int n_tb = p->n_tb;
+  if (g >= p->n_cg * n_tb) return;
+  int cg, tb;
+  if (p->chan_minor) {
+    tb = uniform(g / p->n_cg);
+    cg = g - tb * p->n_cg;
+  } else {
+    cg = uniform(g / n_tb);
+    tb = g - cg * n_tb;
+  }
+  const int t0 = uniform((tb * p->nw + w) * R);  // first output row of the wave
+  if (t0 >= p->n_rows) return;                   // no barriers below: waves leave freely
+  const int64_t c = (int64_t)cg * kWave + lane;
+  const bool cval = c < p->n_ch;
+  const uint32_t rowb = (uint32_t)p->n_ch * 4u;
+  const uint32_t cb = (uint32_t)c * 4u;
+
+  float acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+
+  const int n_chunks = p->n_chunks;
+  for (int q = 0; q < n_chunks; ++q) {
+    const int k0 = q * KC;
+    // input rows of this chunk: xw[i] is input row t0 - k0 - (KC - 1) + i,
+    // u0 the same row counted from the input base
+    const int u0 = uniform(t0 + p->xoff - k0 - (KC - 1));
+    float xw[NX];
+    const uint32_t rb = fresh(rowb);  // row offsets formed here, not held across chunks
+    if (u0 >= 0) {
+      const __amdgpu_buffer_rsrc_t rx = rsrc(p->x, p->range);
+      const uint32_t vo = cval ? (uint32_t)u0 * rb + cb : kOffInvalid;
+      // newest rows first: they are the ones the first taps need
+#pragma unroll
+      for (int i = NX - 1; i >= 0; --i) xw[i] = buf_ld(rx, vo + (uint32_t)i * rb);
+    } else {
+      // the chunk reaches back before the input: rows -(M - 1) .. -1 come from
+      // the carried history, rows further back (zero taps only) read 0
+      const __amdgpu_buffer_rsrc_t rx = rsrc(p->x, p->range);
+      const __amdgpu_buffer_rsrc_t rh = rsrc(p->hin, p->hrange);
+      const int hm = p->hm;
+#pragma unroll
+      for (int i = NX - 1; i >= 0; --i) {
+        const int u = u0 + i;
+        const uint32_t ox = cval && u >= 0 ? (uint32_t)u * rb + cb : kOffInvalid;
+        const uint32_t oh = cval && u < 0 && u >= -hm ? (uint32_t)(u + hm) * rb + cb : kOffInvalid;
+        const float a = buf_ld(rx, ox), b = buf_ld(rh, oh);
+        xw[i] = u >= 0 ? a : b;
+      }
+    }
+    if (q == 0) {
+      // the wave's own rows (xw[KC - 1 + r]) that end the chunk become history
+      const int hs = p->hs, n_rows = p->n_rows;
+      if (t0 + R > hs) {
+        const __amdgpu_buffer_rsrc_t ro = rsrc(p->hout, p->hrange);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int t = t0 + r;
+          const uint32_t o = cval && t >= hs && t < n_rows ? (uint32_t)(t - hs) * rb + cb : kOffInvalid;
+          buf_st(ro, o, xw[KC - 1 + r]);
+        }
+      }
+      // a chunk shorter than M - 1 rows keeps the newest old history rows
+      const int hcopy = p->hcopy;
+      if (t0 == 0 && hcopy > 0) {
+        const __amdgpu_buffer_rsrc_t rh = rsrc(p->hin, p->hrange);
+        const __amdgpu_buffer_rsrc_t ro = rsrc(p->hout, p->hrange);
+        const int src = p->hsrc;
+        for (int j = 0; j < hcopy; ++j) {
+          const float v = buf_ld(rh, cval ? (uint32_t)(src + j) * rowb + cb : kOffInvalid);
+          buf_st(ro, cval ? (uint32_t)j * rowb + cb : kOffInvalid, v);
+        }
+      }
+    }
+    cfloat *hp = (cfloat *)p->h + k0;
+    float hk[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) hk[k] = hp[k];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = __builtin_fmaf(hk[k], xw[KC - 1 + r - k], acc[r]);
+    }
+  }
+
+  const __amdgpu_buffer_rsrc_t ry = rsrc(p->y, p->out_range);
+  const uint32_t rb = fresh(rowb);
+  const uint32_t vy = cval ? (uint32_t)t0 * rb + cb : kOffInvalid;
+#pragma unroll
+  for (int r = 0; r < R; ++r) buf_st(ry, vy + (uint32_t)r * rb, acc[r]);
+}
+
+// Input rows of the unrolled kernel by age: xr[j] is row t0 + 31 - j, so
+// output row t0 + r takes tap kk from xr[31 - r + kk].  Slab s holds
+// xr[32 s .. 32 s + 31]; the rows before the input come from the history.
+template <int N>
+__device__ __forceinline__ void fir_load_slab(firparams_t p, int t0, bool cval, uint32_t cb, int s, float (&xr)[N]) {
+  constexpr int KC = kFirChunk;
+  const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
+  const int umax = uniform(t0 + p->xoff + KC - 1 - KC * s);  // base row of xr[32 s]
+  const int n = N - KC * s < KC ? N - KC * s : KC;
+  const __amdgpu_buffer_rsrc_t rx = rsrc(p->x, p->range);
+  if (umax - (KC - 1) >= 0) {
+    // offsets step down by a row: an invalid lane starts 31 rows above 2^31
+    const uint32_t vo = cval ? (uint32_t)umax * rb + cb : kOffInvalid + (uint32_t)(KC - 1) * rb;
+#pragma unroll
+    for (int i = 0; i < KC; ++i)
+      if (i < n) xr[KC * s + i] = buf_ld(rx, vo - (uint32_t)i * rb);
+  } else {
+    const __amdgpu_buffer_rsrc_t rh = rsrc(p->hin, p->hrange);
+    const int hm = p->hm;
+#pragma unroll
+    for (int i = 0; i < KC; ++i) {
+      if (i < n) {
+        const int u = umax - i;
+        const uint32_t ox = cval && u >= 0 ? (uint32_t)u * rb + cb : kOffInvalid;
+        const uint32_t oh = cval && u < 0 && u >= -hm ? (uint32_t)(u + hm) * rb + cb : kOffInvalid;
+        const float a = buf_ld(rx, ox), b = buf_ld(rh, oh);
+        xr[KC * s + i] = u >= 0 ? a : b;
+      }
+    }
+  }
+}
+
+// Taps [KC/2 * h, KC/2 * (h + 1)) of chunk Q, in ascending order.
+template <int N, int Q, int H>
+__device__ __forceinline__ void fir_half(const float (&hk)[kFirChunk], const float (&xr)[N],
+                                         float (&acc)[kFirChunk]) {
+  constexpr int KC = kFirChunk;
+#pragma unroll
+  for (int k = H * KC / 2; k < (H + 1) * KC / 2; ++k) {
+#pragma unroll
+    for (int r = 0; r < KC; ++r) acc[r] = __builtin_fmaf(hk[k], xr[KC - 1 - r + KC * Q + k], acc[r]);
+  }
+}
+
+// Chunk Q of NCH: first half of its taps, then the next slab and the next
+// chunk's taps are fetched, then the second half; the next chunk follows.
+template <int NCH, int Q, int N>
+__device__ __forceinline__ void fir_chunk(firparams_t p, int t0, bool cval, uint32_t cb, float (&xr)[N],
+                                          float (&hk)[kFirChunk], float (&acc)[kFirChunk]) {
+  constexpr int KC = kFirChunk;
+  fir_half<N, Q, 0>(hk, xr, acc);
+  float hn[KC];
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (Q + 2 <= NCH) fir_load_slab(p, t0, cval, cb, Q + 2, xr);
+  if constexpr (Q + 1 < NCH) {
+    cfloat *hp = (cfloat *)p->h + KC * (Q + 1);
+#pragma unroll
+    for (int e = 0; e < KC; ++e) hn[e] = hp[e];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  fir_half<N, Q, 1>(hk, xr, acc);
+  if constexpr (Q + 1 < NCH) {
+#pragma unroll
+    for (int e = 0; e < KC; ++e) hk[e] = hn[e];
+    fir_chunk<NCH, Q + 1>(p, t0, cval, cb, xr, hk, acc);
+  }
+}
+
+// The same computation for NCH <= 2 tap chunks and 32 output rows, unrolled:
+// consecutive chunks share a 32-row slab (so each input row is loaded once
+// per wave), the next slab and the next chunk's taps are fetched halfway
+// through a chunk, into the registers of rows that chunk no longer needs,
+// and the FMAs keep the ascending tap order (same bits as fir_kernel).
+template <int NCH>
+__global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
+  constexpr int KC = kFirChunk, R = KC, N = KC * NCH + KC - 1;
+  firparams_t p = firparams();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = uniform(threadIdx.x / kWave);
+  const int g = group_of(p->per_xcd);
+  const int n_tb = p->n_tb;
+  if (g >= p->n_cg * n_tb) return;
+  int cg, tb;
+  if (p->chan_minor) {
+    tb = uniform(g / p->n_cg);
+    cg = g - tb * p->n_cg;
+  } else {
+    cg = uniform(g / n_tb);
+    tb = g - cg * n_tb;
+  }
+  const int t0 = uniform((tb * p->nw + w) * R);
+  if (t0 >= p->n_rows) return;
+  const int64_t c = (int64_t)cg * kWave + lane;
+  const bool cval = c < p->n_ch;
+  const uint32_t cb = (uint32_t)c * 4u;
+
+  float xr[N];
+  fir_load_slab(p, t0, cval, cb, 0, xr);
+  fir_load_slab(p, t0, cval, cb, 1, xr);
+  {
+    const int hs = p->hs, n_rows = p->n_rows;
+    if (t0 + R > hs) {
+      const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
+      const __amdgpu_buffer_rsrc_t ro = rsrc(p->hout, p->hrange);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int t = t0 + r;
+        const uint32_t o = cval && t >= hs && t < n_rows ? (uint32_t)(t - hs) * rb + cb : kOffInvalid;
+        buf_st(ro, o, xr[KC - 1 - r]);
+      }
+    }
+    const int hcopy = p->hcopy;
+    if (t0 == 0 && hcopy > 0) {
+      const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
+      const __amdgpu_buffer_rsrc_t rh = rsrc(p->hin, p->hrange);
+      const __amdgpu_buffer_rsrc_t ro = rsrc(p->hout, p->hrange);
+      const int src = p->hsrc;
+      for (int j = 0; j < hcopy; ++j) {
+        const float v = buf_ld(rh, cval ? (uint32_t)(src + j) * rb + cb : kOffInvalid);
+        buf_st(ro, cval ? (uint32_t)j * rb + cb : kOffInvalid, v);
+      }
+    }
+  }
+
+  float acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+  float hk[KC];
+  {
+    cfloat *hp = (cfloat *)p->h;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) hk[k] = hp[k];
+  }
+  fir_chunk<NCH, 0>(p, t0, cval, cb, xr, hk, acc);
+
+  const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
+  const __amdgpu_buffer_rsrc_t ry = rsrc(p->y, p->out_range);
+  const uint32_t vy = cval ? (uint32_t)t0 * rb + cb : kOffInvalid;
+#pragma unroll
+  for (int r = 0; r < R; ++r) buf_st(ry, vy + (uint32_t)r * rb, acc[r]);
+}
+
+}  // namespace
+
+hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream) {
+  if (p.nw < 1 || p.nw > kMaxWaves || p.n_rows < 1 || p.n_chunks < 1 || p.n_cg < 1 || p.n_tb < 1 ||
+      (int64_t)p.n_cg * p.n_tb > 8LL * p.per_xcd)
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)grid_for(p.per_xcd));
+  const dim3 block((unsigned)(p.nw * kWave));
+  // unrolled up to 64 taps; beyond, its live rows would cost occupancy
+  if (R == 32 && p.n_chunks == 1) {
+    hipLaunchKernelGGL(fir_kernel_u<1>, grid, block, 0, stream, p);
+  } else if (R == 32 && p.n_chunks == 2) {
+    hipLaunchKernelGGL(fir_kernel_u<2>, grid, block, 0, stream, p);
+  } else if (R == 16) {
+    hipLaunchKernelGGL(fir_kernel<16>, grid, block, 0, stream, p);
+  } else if (R == 32) {
+    hipLaunchKernelGGL(fir_kernel<32>, grid, block, 0, stream, p);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace filark

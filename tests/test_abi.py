@@ -98,6 +98,19 @@ def test_null_and_range_errors_without_gpu(F):
     assert L.filark_trigger_init(None, 2.0, 1.0, 4, vp(0)) == F.EINVAL
     assert L.filark_trigger_process(vp(0), vp(0), 4, 4, vp(0), 0, vp(0), vp(0)) == F.EINVAL
     assert L.filark_trigger_destroy(vp(0)) == F.OK
+    # FIR: tap count, non-finite taps, channel count, null handles
+    taps = np.ones(4)
+    assert L.filark_fir_init(ctypes.byref(h), taps.ctypes.data_as(D), 0, 4, vp(0)) == F.EINVAL
+    assert L.filark_fir_init(ctypes.byref(h), np.ones(1025).ctypes.data_as(D), 1025, 4, vp(0)) == F.EINVAL
+    assert L.filark_fir_init(ctypes.byref(h), np.array([1.0, np.nan]).ctypes.data_as(D), 2, 4, vp(0)) == F.EINVAL
+    assert L.filark_fir_init(ctypes.byref(h), np.array([1.0, 1e39]).ctypes.data_as(D), 2, 4, vp(0)) == F.EINVAL
+    assert L.filark_fir_init(ctypes.byref(h), taps.ctypes.data_as(D), 4, 0, vp(0)) == F.EINVAL
+    assert L.filark_fir_init(ctypes.byref(h), None, 4, 4, vp(0)) == F.EINVAL
+    assert L.filark_fir_init(None, taps.ctypes.data_as(D), 4, 4, vp(0)) == F.EINVAL
+    assert L.filark_fir_process(vp(0), vp(0), vp(0), 4, 4, vp(0)) == F.EINVAL
+    assert L.filark_fir_set_tile(vp(0), 32, 4, 0) == F.EINVAL
+    assert L.filark_fir_state_get(vp(0), vp(0), vp(0)) == F.EINVAL
+    assert L.filark_fir_destroy(vp(0)) == F.OK
     assert L.filark_last_error()
 
 

@@ -1,0 +1,171 @@
+"""GPU parity of the realtime FIR with carried history against the oracle, on
+the exact FP32 input the GPU saw (upcast).
+
+Bar: element by element, |y_gpu - y_oracle| <= (M + 2) 2^-24 sum_k |h_k| |x_{t-k}|
+(+ 1e-37), the rounding bound of M FP32 FMAs after rounding the taps to FP32;
+the bound itself comes from the oracle run on |h| and |x|.  Beyond parity:
+chunked == one-shot bit for bit on the GPU (every output takes its taps in
+one fixed order), every tile gives the same bits, the carried history is the
+last M - 1 input rows exactly, and state set/get round-trips.
+Shapes: one sample, chunks shorter than the history, ragged channel groups
+and row blocks, tap counts that are and are not multiples of the 32-tap
+chunk, and a million-channel record split over several launch windows.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_20132_amd as F
+
+    F.lib()
+    return F
+
+
+def _orc():
+    import oracle
+
+    return oracle
+
+
+def _taps(M, kind, seed):
+    if kind == "random":
+        return np.random.default_rng(seed).standard_normal(M)
+    # windowed-sinc lowpass at a quarter of the sample rate
+    n = np.arange(M) - (M - 1) / 2
+    return 0.5 * np.sinc(0.5 * n) * np.hamming(M) if M > 1 else np.ones(1)
+
+
+def _check(y, x, h, orc, hist=None):
+    """y (GPU, [n_t, n_ch]) against the oracle on x (float32 numpy) from the
+    given starting history, within the FMA rounding bound."""
+    n_ch = x.shape[1]
+    f = orc.Fir(h, n_ch)
+    fa = orc.Fir(np.abs(h), n_ch)
+    if hist is not None:
+        f.hist[:] = hist
+        fa.hist[:] = np.abs(hist)
+    xd = x.astype(np.float64)
+    ref = f.process(xd)
+    bound = (len(h) + 2) * 2.0 ** -24 * fa.process(np.abs(xd)) + 1e-37
+    err = np.abs(y.astype(np.float64) - ref)
+    assert np.all(err <= bound), f"max err/bound {np.max(err / bound):.3g}"
+    return f
+
+
+@pytest.mark.parametrize("n_ch,n_t", [(1, 1), (7, 100), (65, 129), (130, 1537), (300, 5000)])
+@pytest.mark.parametrize("M,kind", [(1, "random"), (2, "random"), (17, "sinc"), (32, "random"), (33, "sinc"),
+                                    (64, "random"), (101, "sinc")])
+def test_fir_matches_oracle(F, n_ch, n_t, M, kind):
+    orc = _orc()
+    h = _taps(M, kind, M)
+    g = torch.Generator(device="cuda").manual_seed(400 + n_ch + M)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    f = F.Fir(h, n_ch)
+    y = f.process(x)
+    torch.cuda.synchronize()
+    of = _check(y.cpu().numpy(), x.cpu().numpy(), h, orc)
+    if M > 1:
+        np.testing.assert_array_equal(f.get_state(), of.hist.astype(np.float32))
+    f.close()
+
+
+@pytest.mark.parametrize("M", [2, 64, 101])
+def test_chunked_equals_one_shot_bitwise(F, M):
+    n_ch, n_t = 200, 3000
+    h = _taps(M, "random", 7)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    one = F.Fir(h, n_ch).process(x)
+    f = F.Fir(h, n_ch)
+    parts, t = [], 0
+    for n in [0, 1, 5, M - 1, 0, 700, 1, 1]:
+        parts.append(f.process(x[t:t + n].contiguous()))
+        t += n
+    parts.append(f.process(x[t:].contiguous()))
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat(parts), one)
+    np.testing.assert_array_equal(f.get_state(), x[n_t - (M - 1):].cpu().numpy())
+
+
+@pytest.mark.parametrize("rows,waves,order", [(16, 1, 0), (16, 4, 1), (32, 1, 1), (32, 8, 0), (16, 8, 1), (32, 4, 1)])
+def test_every_tile_gives_the_same_bits(F, rows, waves, order):
+    n_ch, n_t, M = 129, 2051, 64
+    h = _taps(M, "sinc", 0)
+    g = torch.Generator(device="cuda").manual_seed(12)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    ref = F.Fir(h, n_ch)
+    a = [ref.process(x[:1000].contiguous()), ref.process(x[1000:].contiguous())]
+    f = F.Fir(h, n_ch)
+    f.set_tile(rows, waves, order)
+    b = [f.process(x[:1000].contiguous()), f.process(x[1000:].contiguous())]
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat(a), torch.cat(b))
+    np.testing.assert_array_equal(f.get_state(), ref.get_state())
+
+
+def test_state_set_continues_a_stream(F):
+    orc = _orc()
+    n_ch, M = 70, 40
+    h = _taps(M, "random", 3)
+    rng = np.random.default_rng(5)
+    hist = rng.standard_normal((M - 1, n_ch)).astype(np.float32)
+    f = F.Fir(h, n_ch)
+    f.set_state(hist)
+    np.testing.assert_array_equal(f.get_state(), hist)
+    x = torch.from_numpy(rng.standard_normal((500, n_ch)).astype(np.float32)).cuda()
+    y = f.process(x)
+    torch.cuda.synchronize()
+    _check(y.cpu().numpy(), x.cpu().numpy(), h, orc, hist=hist.astype(np.float64))
+    # a chunk shorter than the history keeps the newest old rows in front
+    f.set_state(hist)
+    x2 = torch.from_numpy(rng.standard_normal((10, n_ch)).astype(np.float32)).cuda()
+    f.process(x2)
+    np.testing.assert_array_equal(f.get_state(), np.concatenate([hist[10:], x2.cpu().numpy()]))
+
+
+def test_errors(F):
+    h = _taps(16, "random", 1)
+    f = F.Fir(h, 8)
+    x = torch.zeros((100, 8), device="cuda")
+    with pytest.raises(F.FilarkError):
+        f.process(x, x)  # in place: neighbouring outputs read the same inputs
+    with pytest.raises(F.FilarkError):
+        f.process(torch.zeros((100, 9), device="cuda"))
+    with pytest.raises(F.FilarkError):
+        f.set_tile(48, 4)
+    with pytest.raises(F.FilarkError):
+        f.set_tile(32, 4, 2)
+    with pytest.raises(F.FilarkError):
+        F.Fir(np.ones(64), 1 << 23)  # rows of 32 MiB: the taps' reach does not fit a launch
+
+
+def test_million_channels_over_several_launch_windows(F):
+    """1,000,003 channels x 700 rows in two chunks: every launch window is a
+    few hundred rows, so windows meet inside both chunks; sampled channels
+    (each group edge, the ragged last group) against the oracle."""
+    orc = _orc()
+    n_ch, M = 1_000_003, 64
+    h = _taps(M, "sinc", 0)
+    g = torch.Generator(device="cuda").manual_seed(13)
+    x = torch.randn((700, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    f = F.Fir(h, n_ch)
+    y = torch.cat([f.process(x[:300].contiguous()), f.process(x[300:].contiguous())])
+    torch.cuda.synchronize()
+    cols = np.array([0, 1, 63, 64, 65, 500_000, 999_935, 999_936, n_ch - 2, n_ch - 1])
+    idx = torch.from_numpy(cols).cuda()
+    xs = x.index_select(1, idx).cpu().numpy()
+    ys = y.index_select(1, idx).cpu().numpy()
+    _check(ys, xs, h, orc)
+    st = f.get_state()
+    np.testing.assert_array_equal(st[:, cols], xs[700 - (M - 1):])
+    del x, y
+    torch.cuda.empty_cache()
