@@ -298,6 +298,90 @@ def ema_leg(F, torch, dev, steps: int, parity: bool):
     return res
 
 
+def fir_taps(M: int = 64):
+    """Windowed-sinc (Hamming) lowpass at a quarter of the sample rate."""
+    import numpy as np
+
+    n = np.arange(M) - (M - 1) / 2
+    return 0.5 * np.sinc(0.5 * n) * np.hamming(M)
+
+
+# FP32 FMA issue rate without packed FP32 (the library is built without it):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz.
+FP32_VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def fir_leg(F, torch, dev, steps: int, parity: bool):
+    """Realtime FIR (64-tap lowpass, history carried) over the plain-forward
+    record: 6000 ch x 90,000 samples in 60 chunks of 1500, and the same record
+    in one call.  8 B and 2 M flops per channel-sample algorithmic.  Parity:
+    16 sampled channels against the oracle within the FMA rounding bound."""
+    import numpy as np
+
+    import synth
+
+    w = synth.make_config2(device=dev)
+    x = w.x
+    n_t, n_ch = x.shape
+    h = fir_taps(64)
+    M = len(h)
+    y = torch.empty_like(x)
+    f = F.Fir(h, n_ch)
+
+    def chunked():
+        for a in range(0, n_t, w.chunk):
+            f.process(x[a:a + w.chunk], y[a:a + w.chunk])
+
+    def one_shot():
+        f.process(x, y)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms = timed(chunked)
+    ms1 = timed(one_shot)
+    n = n_ch * n_t
+    res = {"workload": f"realtime FIR, {M}-tap lowpass, {n_ch} ch x {n_t} samples in chunks of {w.chunk}",
+           "ms_per_step": ms, "value": n / (ms / 1e3), "unit": "channel-samples/s",
+           "algorithmic_gbs": n * 8 / (ms / 1e3) / 1e9, "tflops": n * 2 * M / (ms / 1e3) / 1e12,
+           "one_shot": {"ms_per_step": ms1, "value": n / (ms1 / 1e3), "algorithmic_gbs": n * 8 / (ms1 / 1e3) / 1e9,
+                        "tflops": n * 2 * M / (ms1 / 1e3) / 1e12}}
+    res["roofline"] = {"bound": "alu", "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "achieved": res["tflops"], "frac": res["tflops"] / FP32_VALU_PEAK_TFLOPS,
+                       "one_shot_frac": res["one_shot"]["tflops"] / FP32_VALU_PEAK_TFLOPS,
+                       "hbm_frac": res["algorithmic_gbs"] / 8000.0}
+    log(f"[bench] FIR {ms:.3f} ms/step chunked ({res['tflops']:.1f} TFLOP/s, {res['algorithmic_gbs']:.0f} GB/s), "
+        f"{ms1:.3f} ms one-shot ({res['one_shot']['tflops']:.1f} TFLOP/s)")
+    if parity:
+        import oracle
+
+        cols = np.random.default_rng(14).choice(n_ch, 16, replace=False)
+        tc = torch.as_tensor(cols, device=dev)
+        f2 = F.Fir(h, n_ch)
+        for a in range(0, n_t, w.chunk):
+            f2.process(x[a:a + w.chunk], y[a:a + w.chunk])
+        torch.cuda.synchronize()
+        xs = x[:, tc].double().cpu().numpy()
+        yo = oracle.Fir(h, len(cols)).process(xs)
+        bound = (M + 2) * 2.0 ** -24 * oracle.Fir(np.abs(h), len(cols)).process(np.abs(xs)) + 1e-37
+        yg = y[:, tc].double().cpu().numpy()
+        worst = float(np.max(np.abs(yg - yo) / bound))
+        res["parity"] = {"channels": len(cols), "max_err_over_bound": worst, "bound": "(M + 2) 2^-24 sum |h||x|",
+                         "ok": worst <= 1.0}
+        log(f"[bench] FIR parity on {len(cols)} channels: max error / bound {worst:.3f}")
+        f2.close()
+    f.close()
+    return res
+
+
 def trigger_leg(F, torch, dev, steps: int, parity: bool):
     """Two-threshold trigger (monitor events) on a cf-shaped record of the
     plain-forward shape: 6000 ch x 90,000 samples in 60 chunks of 1500,
@@ -450,6 +534,7 @@ def main():
     ap.add_argument("--no-trigger", action="store_true")
     ap.add_argument("--no-filtfilt", action="store_true")
     ap.add_argument("--no-ema", action="store_true")
+    ap.add_argument("--no-fir", action="store_true")
     ap.add_argument("--n-ch", type=int, default=6000)
     ap.add_argument("--n-t", type=int, default=90_000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -620,6 +705,10 @@ def main():
     if not args.no_ema:
         ema = ema_leg(F, torch, dev, 5, not args.no_parity)
 
+    fir = None
+    if not args.no_fir:
+        fir = fir_leg(F, torch, dev, 5, not args.no_parity)
+
     fwd_adj = None
     if not args.no_adjoint:
         fwd_adj = fwd_adjoint_leg(F, torch, dev, 3, not args.no_parity)
@@ -654,7 +743,7 @@ def main():
                                "y and cf written",
                    "io": "fp32", "filter_arith": "fp64", "stalta_arith": "fp32 block / fp64 carry"},
         "roofline": roofline, "cpu_baseline": cpu, "parity": parity, "graph_replay": graph,
-        "fwd_adjoint": fwd_adj, "batched": batched, "trigger": trig, "zero_phase": ff, "running_agc": ema,
+        "fwd_adjoint": fwd_adj, "batched": batched, "trigger": trig, "zero_phase": ff, "running_agc": ema, "fir": fir,
     }
     print(json.dumps(out))
 

@@ -317,8 +317,9 @@ filark_status filark_ema_destroy(filark_ema_t st);
  *   _set_tile  output rows per wave (16 or 32), waves per workgroup (1..8)
  *              and workgroup order (0: each XCD walks along time within its
  *              channel groups; 1: each XCD walks its rows across all channel
- *              groups first); default 32 x 4, order 1.  Any tile gives the
- *              same bits.
+ *              groups first; 2: each XCD owns an eighth of the channel groups
+ *              and sweeps its rows across them); default 32 x 1, order 2.
+ *              Any tile gives the same bits.
  *   _process   in / out: device FP32 [n_t][n_ch], time-major; they must not
  *              overlap (neighbouring outputs read the same inputs).
  *              Asynchronous on `stream`; n_t = 0 is a no-op.  Successive

@@ -546,7 +546,7 @@ class Fir:
         _check(lib().filark_fir_init(ctypes.byref(self._h), h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                      self.n_taps, self.n_ch, _stream(stream)))
 
-    def set_tile(self, rows: int, waves: int, order: int = 1):
+    def set_tile(self, rows: int, waves: int, order: int = 2):
         _check(lib().filark_fir_set_tile(self._h, int(rows), int(waves), int(order)))
 
     def process(self, x, out=None, stream=None):

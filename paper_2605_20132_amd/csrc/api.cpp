@@ -231,8 +231,8 @@ struct filark_fir_state {
   float *d_h = nullptr;           // [n_pad] FP32 taps, zero past M
   float *d_hist[2] = {};          // [max(M - 1, 1)][n_ch] each; d_hist[cur] is current
   int cur = 0;
-  int rows = 32, waves = 4;       // output rows per wave, waves per workgroup
-  int order = 1;                  // workgroup order: across channel groups first (whole rows per XCD)
+  int rows = 32, waves = 1;       // output rows per wave, waves per workgroup
+  int order = 2;                  // workgroup order: a channel slab per XCD, swept row block by row block
 };
 
 struct filark_trigger_state {
@@ -1371,8 +1371,8 @@ filark_status filark_fir_init(filark_fir_t *out, const double *taps, int n_taps,
 
 filark_status filark_fir_set_tile(filark_fir_t st, int rows, int waves, int order) {
   if (!st) return fail(FILARK_EINVAL, "null state");
-  if (!fir_rows_ok(rows) || waves < 1 || waves > kMaxWaves || (order != 0 && order != 1))
-    return fail(FILARK_EINVAL, "FIR tile %dx%d order %d: rows must be 16 or 32, waves 1..%d, order 0 or 1", rows,
+  if (!fir_rows_ok(rows) || waves < 1 || waves > kMaxWaves || order < 0 || order > 2)
+    return fail(FILARK_EINVAL, "FIR tile %dx%d order %d: rows must be 16 or 32, waves 1..%d, order 0..2", rows,
                 waves, order, kMaxWaves);
   const int r0 = st->rows, w0 = st->waves;
   st->rows = rows;
@@ -1434,7 +1434,7 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
       e = hipErrorInvalidValue;
       break;
     }
-    p.per_xcd = (int32_t)((n_wg + 7) / 8);
+    p.per_xcd = st->order == 2 ? (p.n_cg + 7) / 8 : (int32_t)((n_wg + 7) / 8);
     e = launch_fir(p, st->rows, stream);
   }
   if (prev_dev != st->device) (void)hipSetDevice(prev_dev);

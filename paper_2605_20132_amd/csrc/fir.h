@@ -33,7 +33,7 @@ struct FirParams {
   int32_t hsrc;       // first carried-over row of hin (n_t)
   int32_t n_cg, n_tb;  // channel groups of 64, workgroups along the window's rows
   int32_t per_xcd, nw;
-  int32_t chan_minor;  // workgroup order: 0 = along time within a channel group, 1 = across channel groups first
+  int32_t chan_minor;  // workgroup order 0, 1 or 2 (fir_tile_of); for 2, per_xcd is the slab width in groups
 };
 
 // Output rows per wave that the kernel is compiled for.

@@ -13,10 +13,11 @@
 // ascending order, whatever the chunking, so a chunked run equals the one-shot
 // run bit for bit.  The kernel is bound by FMA issue at long filters and by
 // HBM at short ones; halo rows that neighbouring waves share are re-read from
-// L1/L2, not HBM.  By default each XCD walks its rows across all channel
-// groups before moving on in time, so the XCD streams whole rows, and the
-// halo of a row block was read by the same XCD one sweep earlier.  Up to 64
-// taps a second, unrolled kernel loads each input row once per wave.
+// L1/L2, not HBM.  By default each XCD owns an eighth of the channel groups
+// and sweeps its rows block by block across them (3 KB of every row at 6000
+// channels), so the halo of a block was read into the same L2 one sweep
+// earlier.  Up to 64 taps a second, unrolled kernel loads each input row once
+// per wave.
 #include "device.h"
 #include "fir.h"
 
@@ -28,6 +29,35 @@ typedef const FILARK_CONST float cfloat;
 typedef const FILARK_CONST FirParams *firparams_t;
 __device__ __forceinline__ firparams_t firparams() { return dev::kparams<FirParams>(); }
 
+// Channel group and row block of this workgroup; false past the grid's work.
+// Order 0: XCD x takes a contiguous run of (group, block) pairs, blocks
+// fastest.  Order 1: the same with groups fastest, so an XCD streams whole
+// rows.  Order 2: XCD x takes the channel slab [x s, (x + 1) s) of s = per_xcd
+// groups and sweeps its rows block by block across the slab, so the halo rows
+// of a block were read into the same L2 by the block before.
+__device__ __forceinline__ bool fir_tile_of(firparams_t p, int &cg, int &tb) {
+  const int n_tb = p->n_tb, n_cg = p->n_cg, order = p->chan_minor;
+  if (order == 2) {
+    const int x = (int)blockIdx.x & 7, i = (int)blockIdx.x >> 3, s = p->per_xcd;
+    const int c0 = x * s;
+    const int cs = n_cg - c0 < s ? n_cg - c0 : s;  // groups in this XCD's slab
+    if (cs <= 0 || i >= cs * n_tb) return false;
+    tb = uniform(i / cs);
+    cg = uniform(c0 + (i - tb * cs));
+    return true;
+  }
+  const int g = group_of(p->per_xcd);
+  if (g >= n_cg * n_tb) return false;
+  if (order == 1) {
+    tb = uniform(g / n_cg);
+    cg = g - tb * n_cg;
+  } else {
+    cg = uniform(g / n_tb);
+    tb = g - cg * n_tb;
+  }
+  return true;
+}
+
 template <int R>
 __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
   constexpr int KC = kFirChunk;
@@ -35,17 +65,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
   firparams_t p = firparams();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x / kWave);
-  const int g = group_of(p->per_xcd);
-  const int n_tb = p->n_tb;
-  if (g >= p->n_cg * n_tb) return;
   int cg, tb;
-  if (p->chan_minor) {
-    tb = uniform(g / p->n_cg);
-    cg = g - tb * p->n_cg;
-  } else {
-    cg = uniform(g / n_tb);
-    tb = g - cg * n_tb;
-  }
+  if (!fir_tile_of(p, cg, tb)) return;
   const int t0 = uniform((tb * p->nw + w) * R);  // first output row of the wave
   if (t0 >= p->n_rows) return;                   // no barriers below: waves leave freely
   const int64_t c = (int64_t)cg * kWave + lane;
@@ -207,17 +228,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
   firparams_t p = firparams();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x / kWave);
-  const int g = group_of(p->per_xcd);
-  const int n_tb = p->n_tb;
-  if (g >= p->n_cg * n_tb) return;
   int cg, tb;
-  if (p->chan_minor) {
-    tb = uniform(g / p->n_cg);
-    cg = g - tb * p->n_cg;
-  } else {
-    cg = uniform(g / n_tb);
-    tb = g - cg * n_tb;
-  }
+  if (!fir_tile_of(p, cg, tb)) return;
   const int t0 = uniform((tb * p->nw + w) * R);
   if (t0 >= p->n_rows) return;
   const int64_t c = (int64_t)cg * kWave + lane;
@@ -274,9 +286,14 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
 
 hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream) {
   if (p.nw < 1 || p.nw > kMaxWaves || p.n_rows < 1 || p.n_chunks < 1 || p.n_cg < 1 || p.n_tb < 1 ||
-      (int64_t)p.n_cg * p.n_tb > 8LL * p.per_xcd)
+      p.chan_minor < 0 || p.chan_minor > 2)
     return hipErrorInvalidValue;
-  const dim3 grid((unsigned)grid_for(p.per_xcd));
+  // order 2: per_xcd is the slab width in groups, each XCD runs slab x n_tb workgroups
+  const int64_t per = p.chan_minor == 2 ? (int64_t)p.per_xcd * p.n_tb : p.per_xcd;
+  if (p.chan_minor == 2 ? 8LL * p.per_xcd < p.n_cg : (int64_t)p.n_cg * p.n_tb > 8LL * p.per_xcd)
+    return hipErrorInvalidValue;
+  if (per > ((int64_t)1 << 28)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(8 * per));
   const dim3 block((unsigned)(p.nw * kWave));
   // unrolled up to 64 taps; beyond, its live rows would cost occupancy
   if (R == 32 && p.n_chunks == 1) {

@@ -96,7 +96,8 @@ def test_chunked_equals_one_shot_bitwise(F, M):
     np.testing.assert_array_equal(f.get_state(), x[n_t - (M - 1):].cpu().numpy())
 
 
-@pytest.mark.parametrize("rows,waves,order", [(16, 1, 0), (16, 4, 1), (32, 1, 1), (32, 8, 0), (16, 8, 1), (32, 4, 1)])
+@pytest.mark.parametrize("rows,waves,order", [(16, 1, 0), (16, 4, 1), (32, 1, 1), (32, 8, 0), (16, 8, 1), (32, 4, 1),
+                                               (32, 1, 2), (16, 2, 2), (32, 4, 2)])
 def test_every_tile_gives_the_same_bits(F, rows, waves, order):
     n_ch, n_t, M = 129, 2051, 64
     h = _taps(M, "sinc", 0)
@@ -110,6 +111,21 @@ def test_every_tile_gives_the_same_bits(F, rows, waves, order):
     torch.cuda.synchronize()
     assert torch.equal(torch.cat(a), torch.cat(b))
     np.testing.assert_array_equal(f.get_state(), ref.get_state())
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_orders_on_few_channel_groups(F, order):
+    """1 to 9 channel groups of 64 (fewer groups than XCDs for order 2)."""
+    orc = _orc()
+    h = _taps(64, "random", 9)
+    for n_ch in (1, 64, 130, 513):
+        g = torch.Generator(device="cuda").manual_seed(n_ch)
+        x = torch.randn((777, n_ch), generator=g, device="cuda", dtype=torch.float32)
+        f = F.Fir(h, n_ch)
+        f.set_tile(32, 1, order)
+        y = f.process(x)
+        torch.cuda.synchronize()
+        _check(y.cpu().numpy(), x.cpu().numpy(), h, orc)
 
 
 def test_state_set_continues_a_stream(F):
@@ -143,7 +159,7 @@ def test_errors(F):
     with pytest.raises(F.FilarkError):
         f.set_tile(48, 4)
     with pytest.raises(F.FilarkError):
-        f.set_tile(32, 4, 2)
+        f.set_tile(32, 4, 3)
     with pytest.raises(F.FilarkError):
         F.Fir(np.ones(64), 1 << 23)  # rows of 32 MiB: the taps' reach does not fit a launch
 
