@@ -78,6 +78,22 @@ def test_fir_matches_oracle(F, n_ch, n_t, M, kind):
     f.close()
 
 
+@pytest.mark.parametrize("M", [63, 65, 96, 128, 129, 1024])
+def test_long_filters_and_kernel_switch(F, M):
+    """Tap counts on both sides of the unrolled kernel's limit (64 taps) up to
+    the maximum, over ragged shapes, in two chunks."""
+    orc = _orc()
+    h = _taps(M, "sinc", M)
+    n_ch, n_t = 97, 2 * M + 333
+    g = torch.Generator(device="cuda").manual_seed(500 + M)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    f = F.Fir(h, n_ch)
+    y = torch.cat([f.process(x[:M // 2 + 1].contiguous()), f.process(x[M // 2 + 1:].contiguous())])
+    torch.cuda.synchronize()
+    of = _check(y.cpu().numpy(), x.cpu().numpy(), h, orc)
+    np.testing.assert_array_equal(f.get_state(), of.hist.astype(np.float32))
+
+
 @pytest.mark.parametrize("M", [2, 64, 101])
 def test_chunked_equals_one_shot_bitwise(F, M):
     n_ch, n_t = 200, 3000
