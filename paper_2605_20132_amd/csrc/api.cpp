@@ -246,9 +246,10 @@ struct filark_trigger_state {
 
 namespace {
 
-// Trigger tile: 48-row blocks, 4 waves, groups of 8 channels (1536-row
-// windows; the kernel is compiled for 48-row blocks only).
-constexpr int kTrigBlock = 48, kTrigWaves = 4, kTrigGroup = 8;
+// Trigger and exponential-average tile: 48-row blocks, 8 waves, groups of
+// 16 channels (1536-row windows, so a 1500-row chunk is one launch; 64-byte
+// row segments per group; the kernels are compiled for 48-row blocks only).
+constexpr int kTrigBlock = 48, kTrigWaves = 8, kTrigGroup = 16;
 
 // Default adjoint tile: 16-sample blocks, 8 waves, groups of 8 channels
 // (windows of 1024 rows).
