@@ -314,7 +314,7 @@ filark_status filark_ema_destroy(filark_ema_t st);
  *   _init      taps: host FP64 [n_taps], finite, applied as FP32;
  *              1 <= n_taps <= 1024; n_ch in [1, 2^24] (and small enough that
  *              (n_taps + 100) rows of n_ch floats stay below 2 GiB).
- *   _set_tile  output rows per wave (16 or 32), waves per workgroup (1..8)
+ *   _set_tile  output rows per wave (16, 32 or 48), waves per workgroup (1..8)
  *              and workgroup order (0: each XCD walks along time within its
  *              channel groups; 1: each XCD walks its rows across all channel
  *              groups first; 2: each XCD owns an eighth of the channel groups

@@ -1324,11 +1324,13 @@ filark_status filark_trigger_destroy(filark_trigger_t st) {
 namespace {
 
 // Rows per FIR launch: every byte offset the kernel forms (window rows plus
-// the taps' reach back and one wave's rows of slack) stays below 2^31.
+// the taps' reach back and one wave's rows of slack) stays below 2^31.  A
+// multiple of 96 x waves, so that 16-, 32- and 48-row waves tile it.
+constexpr int kFirMaxRows = 48;
 int64_t fir_window_rows(const filark_fir_state *st) {
   const int64_t rowb = st->n_ch * 4;
-  const int64_t span = (int64_t)st->rows * st->waves;
-  const int64_t budget = ((int64_t)1 << 31) / rowb - (st->n_pad + st->rows + kFirChunk + 2);
+  const int64_t span = (int64_t)96 * st->waves;
+  const int64_t budget = ((int64_t)1 << 31) / rowb - (st->n_pad + kFirMaxRows + kFirChunk + 2);
   return std::max<int64_t>(0, (budget - (st->n_pad - 1)) / span * span);
 }
 
@@ -1373,7 +1375,7 @@ filark_status filark_fir_init(filark_fir_t *out, const double *taps, int n_taps,
 filark_status filark_fir_set_tile(filark_fir_t st, int rows, int waves, int order) {
   if (!st) return fail(FILARK_EINVAL, "null state");
   if (!fir_rows_ok(rows) || waves < 1 || waves > kMaxWaves || order < 0 || order > 2)
-    return fail(FILARK_EINVAL, "FIR tile %dx%d order %d: rows must be 16 or 32, waves 1..%d, order 0..2", rows,
+    return fail(FILARK_EINVAL, "FIR tile %dx%d order %d: rows must be 16, 32 or 48, waves 1..%d, order 0..2", rows,
                 waves, order, kMaxWaves);
   const int r0 = st->rows, w0 = st->waves;
   st->rows = rows;
@@ -1402,7 +1404,7 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
   if (W < 1) return fail(FILARK_EINVAL, "n_ch too large for this FIR tile");
   const int prev_dev = current_device();
   if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));
-  const int64_t rowb = n_ch * 4, hm = st->n_taps - 1, span = (int64_t)st->rows * st->waves;
+  const int64_t rowb = n_ch * 4, hm = st->n_taps - 1;
   FirParams p;
   std::memset(&p, 0, sizeof p);
   p.h = st->d_h;
@@ -1429,6 +1431,8 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
     p.hs = (int32_t)std::max<int64_t>(std::min<int64_t>(hs, n_rows), -hm);
     p.hcopy = T0 == 0 ? (int32_t)std::max<int64_t>(0, hm - n_t) : 0;
     p.hsrc = (int32_t)std::min<int64_t>(n_t, hm);
+    const int R = st->rows;
+    const int64_t span = (int64_t)R * st->waves;
     p.n_tb = (int32_t)((n_rows + span - 1) / span);
     const int64_t n_wg = (int64_t)p.n_cg * p.n_tb;
     if (n_wg > ((int64_t)1 << 30)) {
@@ -1436,7 +1440,7 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
       break;
     }
     p.per_xcd = st->order == 2 ? (p.n_cg + 7) / 8 : (int32_t)((n_wg + 7) / 8);
-    e = launch_fir(p, st->rows, stream);
+    e = launch_fir(p, R, stream);
   }
   if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "launch failed: %s", hipGetErrorString(e));

@@ -36,8 +36,8 @@ struct FirParams {
   int32_t chan_minor;  // workgroup order 0, 1 or 2 (fir_tile_of); for 2, per_xcd is the slab width in groups
 };
 
-// Output rows per wave that the kernel is compiled for.
-inline bool fir_rows_ok(int R) { return R == 16 || R == 32; }
+// Output rows per wave that the kernels are compiled for.
+inline bool fir_rows_ok(int R) { return R == 16 || R == 32 || R == 48; }
 
 hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream);
 

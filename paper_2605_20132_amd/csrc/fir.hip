@@ -149,14 +149,14 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
   for (int r = 0; r < R; ++r) buf_st(ry, vy + (uint32_t)r * rb, acc[r]);
 }
 
-// Input rows of the unrolled kernel by age: xr[j] is row t0 + 31 - j, so
-// output row t0 + r takes tap kk from xr[31 - r + kk].  Slab s holds
+// Input rows of the unrolled kernel by age: xr[j] is row t0 + R - 1 - j, so
+// output row t0 + r takes tap kk from xr[R - 1 - r + kk].  Slab s holds
 // xr[32 s .. 32 s + 31]; the rows before the input come from the history.
-template <int N>
+template <int R, int N>
 __device__ __forceinline__ void fir_load_slab(firparams_t p, int t0, bool cval, uint32_t cb, int s, float (&xr)[N]) {
   constexpr int KC = kFirChunk;
   const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
-  const int umax = uniform(t0 + p->xoff + KC - 1 - KC * s);  // base row of xr[32 s]
+  const int umax = uniform(t0 + p->xoff + R - 1 - KC * s);  // base row of xr[32 s]
   const int n = N - KC * s < KC ? N - KC * s : KC;
   const __amdgpu_buffer_rsrc_t rx = rsrc(p->x, p->range);
   if (umax - (KC - 1) >= 0) {
@@ -182,34 +182,39 @@ __device__ __forceinline__ void fir_load_slab(firparams_t p, int t0, bool cval, 
 }
 
 // Taps [KC/2 * h, KC/2 * (h + 1)) of chunk Q, in ascending order.
-template <int N, int Q, int H>
-__device__ __forceinline__ void fir_half(const float (&hk)[kFirChunk], const float (&xr)[N],
-                                         float (&acc)[kFirChunk]) {
+template <int R, int N, int Q, int H>
+__device__ __forceinline__ void fir_half(const float (&hk)[kFirChunk], const float (&xr)[N], float (&acc)[R]) {
   constexpr int KC = kFirChunk;
 #pragma unroll
   for (int k = H * KC / 2; k < (H + 1) * KC / 2; ++k) {
 #pragma unroll
-    for (int r = 0; r < KC; ++r) acc[r] = __builtin_fmaf(hk[k], xr[KC - 1 - r + KC * Q + k], acc[r]);
+    for (int r = 0; r < R; ++r) acc[r] = __builtin_fmaf(hk[k], xr[R - 1 - r + KC * Q + k], acc[r]);
   }
 }
 
-// Chunk Q of NCH: first half of its taps, then the next slab and the next
-// chunk's taps are fetched, then the second half; the next chunk follows.
-template <int NCH, int Q, int N>
+// Slabs chunk 0 needs beyond slab 0 (chunk Q reaches slab Q + this).
+template <int R>
+constexpr int fir_reach() {
+  return (R + kFirChunk - 2) / kFirChunk;
+}
+
+// Chunk Q of NCH: first half of its taps, then the next chunk's last slab
+// and taps are fetched, then the second half; the next chunk follows.
+template <int NCH, int Q, int R, int N>
 __device__ __forceinline__ void fir_chunk(firparams_t p, int t0, bool cval, uint32_t cb, float (&xr)[N],
-                                          float (&hk)[kFirChunk], float (&acc)[kFirChunk]) {
-  constexpr int KC = kFirChunk;
-  fir_half<N, Q, 0>(hk, xr, acc);
+                                          float (&hk)[kFirChunk], float (&acc)[R]) {
+  constexpr int KC = kFirChunk, S = Q + 1 + fir_reach<R>();
+  fir_half<R, N, Q, 0>(hk, xr, acc);
   float hn[KC];
   __builtin_amdgcn_sched_barrier(0);
-  if constexpr (Q + 2 <= NCH) fir_load_slab(p, t0, cval, cb, Q + 2, xr);
+  if constexpr (Q + 1 < NCH && KC * S < N) fir_load_slab<R>(p, t0, cval, cb, S, xr);
   if constexpr (Q + 1 < NCH) {
     cfloat *hp = (cfloat *)p->h + KC * (Q + 1);
 #pragma unroll
     for (int e = 0; e < KC; ++e) hn[e] = hp[e];
   }
   __builtin_amdgcn_sched_barrier(0);
-  fir_half<N, Q, 1>(hk, xr, acc);
+  fir_half<R, N, Q, 1>(hk, xr, acc);
   if constexpr (Q + 1 < NCH) {
 #pragma unroll
     for (int e = 0; e < KC; ++e) hk[e] = hn[e];
@@ -217,14 +222,14 @@ __device__ __forceinline__ void fir_chunk(firparams_t p, int t0, bool cval, uint
   }
 }
 
-// The same computation for NCH <= 2 tap chunks and 32 output rows, unrolled:
-// consecutive chunks share a 32-row slab (so each input row is loaded once
-// per wave), the next slab and the next chunk's taps are fetched halfway
-// through a chunk, into the registers of rows that chunk no longer needs,
-// and the FMAs keep the ascending tap order (same bits as fir_kernel).
-template <int NCH>
+// The same computation for NCH <= 2 tap chunks and R = 32 or 48 output rows,
+// unrolled: consecutive chunks share 32-row slabs (so each input row is
+// loaded once per wave), the next slab and the next chunk's taps are fetched
+// halfway through a chunk, into the registers of rows that chunk no longer
+// needs, and the FMAs keep the ascending tap order (same bits as fir_kernel).
+template <int NCH, int R>
 __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
-  constexpr int KC = kFirChunk, R = KC, N = KC * NCH + KC - 1;
+  constexpr int KC = kFirChunk, N = R + KC * NCH - 1;
   firparams_t p = firparams();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x / kWave);
@@ -237,8 +242,9 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
   const uint32_t cb = (uint32_t)c * 4u;
 
   float xr[N];
-  fir_load_slab(p, t0, cval, cb, 0, xr);
-  fir_load_slab(p, t0, cval, cb, 1, xr);
+#pragma unroll
+  for (int s = 0; s <= fir_reach<R>(); ++s)
+    if (KC * s < N) fir_load_slab<R>(p, t0, cval, cb, s, xr);
   {
     const int hs = p->hs, n_rows = p->n_rows;
     if (t0 + R > hs) {
@@ -248,7 +254,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
       for (int r = 0; r < R; ++r) {
         const int t = t0 + r;
         const uint32_t o = cval && t >= hs && t < n_rows ? (uint32_t)(t - hs) * rb + cb : kOffInvalid;
-        buf_st(ro, o, xr[KC - 1 - r]);
+        buf_st(ro, o, xr[R - 1 - r]);
       }
     }
     const int hcopy = p->hcopy;
@@ -282,6 +288,18 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
   for (int r = 0; r < R; ++r) buf_st(ry, vy + (uint32_t)r * rb, acc[r]);
 }
 
+// The kernel a launch with R rows per wave and n_chunks tap chunks runs.
+const void *fir_kernel_for(int R, int n_chunks) {
+  if (R == 32 && n_chunks == 1) return (const void *)fir_kernel_u<1, 32>;
+  if (R == 32 && n_chunks == 2) return (const void *)fir_kernel_u<2, 32>;
+  if (R == 48 && n_chunks == 1) return (const void *)fir_kernel_u<1, 48>;
+  if (R == 48 && n_chunks == 2) return (const void *)fir_kernel_u<2, 48>;
+  if (R == 16) return (const void *)fir_kernel<16>;
+  if (R == 32) return (const void *)fir_kernel<32>;
+  if (R == 48) return (const void *)fir_kernel<48>;
+  return nullptr;
+}
+
 }  // namespace
 
 hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream) {
@@ -296,17 +314,11 @@ hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream) {
   const dim3 grid((unsigned)(8 * per));
   const dim3 block((unsigned)(p.nw * kWave));
   // unrolled up to 64 taps; beyond, its live rows would cost occupancy
-  if (R == 32 && p.n_chunks == 1) {
-    hipLaunchKernelGGL(fir_kernel_u<1>, grid, block, 0, stream, p);
-  } else if (R == 32 && p.n_chunks == 2) {
-    hipLaunchKernelGGL(fir_kernel_u<2>, grid, block, 0, stream, p);
-  } else if (R == 16) {
-    hipLaunchKernelGGL(fir_kernel<16>, grid, block, 0, stream, p);
-  } else if (R == 32) {
-    hipLaunchKernelGGL(fir_kernel<32>, grid, block, 0, stream, p);
-  } else {
-    return hipErrorInvalidValue;
-  }
+  const void *k = fir_kernel_for(R, p.n_chunks);
+  if (!k) return hipErrorInvalidValue;
+  void *args[] = {const_cast<FirParams *>(&p)};
+  const hipError_t e = hipLaunchKernel(k, grid, block, args, 0, stream);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -78,6 +78,27 @@ def test_fir_matches_oracle(F, n_ch, n_t, M, kind):
     f.close()
 
 
+@pytest.mark.parametrize("rows", [16, 32, 48])
+@pytest.mark.parametrize("M", [1, 32, 33, 64, 65, 200])
+def test_rows_per_wave_match_oracle_and_each_other(F, rows, M):
+    """Every rows-per-wave kernel (unrolled up to 64 taps, looped beyond)
+    against the oracle, ragged in rows and channels, through a chunk shorter
+    than the history, and bit for bit against the default tile."""
+    orc = _orc()
+    h = _taps(M, "random", 40 + M)
+    n_ch, n_t = 150, 1000
+    g = torch.Generator(device="cuda").manual_seed(600 + M)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    f = F.Fir(h, n_ch)
+    f.set_tile(rows, 1, 2)
+    cut = max(1, M // 3)
+    y = torch.cat([f.process(x[:cut].contiguous()), f.process(x[cut:].contiguous())])
+    ref = F.Fir(h, n_ch).process(x)
+    torch.cuda.synchronize()
+    _check(y.cpu().numpy(), x.cpu().numpy(), h, orc)
+    assert torch.equal(y, ref)
+
+
 @pytest.mark.parametrize("M", [63, 65, 96, 128, 129, 1024])
 def test_long_filters_and_kernel_switch(F, M):
     """Tap counts on both sides of the unrolled kernel's limit (64 taps) up to
@@ -113,7 +134,8 @@ def test_chunked_equals_one_shot_bitwise(F, M):
 
 
 @pytest.mark.parametrize("rows,waves,order", [(16, 1, 0), (16, 4, 1), (32, 1, 1), (32, 8, 0), (16, 8, 1), (32, 4, 1),
-                                               (32, 1, 2), (16, 2, 2), (32, 4, 2)])
+                                               (32, 1, 2), (16, 2, 2), (32, 4, 2), (48, 1, 2), (48, 4, 0),
+                                               (48, 2, 1)])
 def test_every_tile_gives_the_same_bits(F, rows, waves, order):
     n_ch, n_t, M = 129, 2051, 64
     h = _taps(M, "sinc", 0)
@@ -173,7 +195,7 @@ def test_errors(F):
     with pytest.raises(F.FilarkError):
         f.process(torch.zeros((100, 9), device="cuda"))
     with pytest.raises(F.FilarkError):
-        f.set_tile(48, 4)
+        f.set_tile(64, 4)
     with pytest.raises(F.FilarkError):
         f.set_tile(32, 4, 3)
     with pytest.raises(F.FilarkError):
