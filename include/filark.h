@@ -314,11 +314,13 @@ filark_status filark_ema_destroy(filark_ema_t st);
  *   _init      taps: host FP64 [n_taps], finite, applied as FP32;
  *              1 <= n_taps <= 1024; n_ch in [1, 2^24] (and small enough that
  *              (n_taps + 100) rows of n_ch floats stay below 2 GiB).
- *   _set_tile  output rows per wave (16, 32 or 48), waves per workgroup (1..8)
+ *   _set_tile  output rows per wave (0: 48 for launch windows of 8192 rows
+ *              or more with at most 64 taps, else 32; or 16, 32, 48), waves
+ *              per workgroup (1..8)
  *              and workgroup order (0: each XCD walks along time within its
  *              channel groups; 1: each XCD walks its rows across all channel
  *              groups first; 2: each XCD owns an eighth of the channel groups
- *              and sweeps its rows across them); default 32 x 1, order 2.
+ *              and sweeps its rows across them); default 0 x 1, order 2.
  *              Any tile gives the same bits.
  *   _process   in / out: device FP32 [n_t][n_ch], time-major; they must not
  *              overlap (neighbouring outputs read the same inputs).

@@ -231,7 +231,7 @@ struct filark_fir_state {
   float *d_h = nullptr;           // [n_pad] FP32 taps, zero past M
   float *d_hist[2] = {};          // [max(M - 1, 1)][n_ch] each; d_hist[cur] is current
   int cur = 0;
-  int rows = 32, waves = 1;       // output rows per wave, waves per workgroup
+  int rows = 0, waves = 1;        // output rows per wave (0: by launch), waves per workgroup
   int order = 2;                  // workgroup order: a channel slab per XCD, swept row block by row block
 };
 
@@ -1374,9 +1374,9 @@ filark_status filark_fir_init(filark_fir_t *out, const double *taps, int n_taps,
 
 filark_status filark_fir_set_tile(filark_fir_t st, int rows, int waves, int order) {
   if (!st) return fail(FILARK_EINVAL, "null state");
-  if (!fir_rows_ok(rows) || waves < 1 || waves > kMaxWaves || order < 0 || order > 2)
-    return fail(FILARK_EINVAL, "FIR tile %dx%d order %d: rows must be 16, 32 or 48, waves 1..%d, order 0..2", rows,
-                waves, order, kMaxWaves);
+  if ((rows != 0 && !fir_rows_ok(rows)) || waves < 1 || waves > kMaxWaves || order < 0 || order > 2)
+    return fail(FILARK_EINVAL, "FIR tile %dx%d order %d: rows must be 0 (by launch), 16, 32 or 48, waves 1..%d, "
+                "order 0..2", rows, waves, order, kMaxWaves);
   const int r0 = st->rows, w0 = st->waves;
   st->rows = rows;
   st->waves = waves;
@@ -1431,7 +1431,11 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
     p.hs = (int32_t)std::max<int64_t>(std::min<int64_t>(hs, n_rows), -hm);
     p.hcopy = T0 == 0 ? (int32_t)std::max<int64_t>(0, hm - n_t) : 0;
     p.hsrc = (int32_t)std::min<int64_t>(n_t, hm);
-    const int R = st->rows;
+    // by launch: 48-row waves (3 per SIMD) on long windows of the unrolled
+    // kernels, where their lower halo share pays; 32-row waves (4 per SIMD)
+    // on chunk-sized windows and on the looped kernel, where more waves per
+    // SIMD hide more load latency
+    const int R = st->rows ? st->rows : (n_rows >= 8192 && p.n_chunks <= 2 ? 48 : 32);
     const int64_t span = (int64_t)R * st->waves;
     p.n_tb = (int32_t)((n_rows + span - 1) / span);
     const int64_t n_wg = (int64_t)p.n_cg * p.n_tb;

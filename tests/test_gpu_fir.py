@@ -135,7 +135,7 @@ def test_chunked_equals_one_shot_bitwise(F, M):
 
 @pytest.mark.parametrize("rows,waves,order", [(16, 1, 0), (16, 4, 1), (32, 1, 1), (32, 8, 0), (16, 8, 1), (32, 4, 1),
                                                (32, 1, 2), (16, 2, 2), (32, 4, 2), (48, 1, 2), (48, 4, 0),
-                                               (48, 2, 1)])
+                                               (48, 2, 1), (0, 1, 2), (0, 3, 0)])
 def test_every_tile_gives_the_same_bits(F, rows, waves, order):
     n_ch, n_t, M = 129, 2051, 64
     h = _taps(M, "sinc", 0)
@@ -200,6 +200,26 @@ def test_errors(F):
         f.set_tile(32, 4, 3)
     with pytest.raises(F.FilarkError):
         F.Fir(np.ones(64), 1 << 23)  # rows of 32 MiB: the taps' reach does not fit a launch
+
+
+@pytest.mark.parametrize("M", [64, 100])
+def test_long_window_default_tile_matches_fixed_tiles(F, M):
+    """A 9000-row call (48-row waves by default at 64 taps, 32-row waves at
+    100) against fixed 32- and 48-row tiles bit for bit and the oracle on
+    sampled channels."""
+    orc = _orc()
+    h = _taps(M, "sinc", 3)
+    n_ch, n_t = 200, 9000
+    g = torch.Generator(device="cuda").manual_seed(700 + M)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    y = F.Fir(h, n_ch).process(x)
+    for rows in (32, 48):
+        f = F.Fir(h, n_ch)
+        f.set_tile(rows, 1, 2)
+        assert torch.equal(f.process(x), y)
+    torch.cuda.synchronize()
+    cols = [0, 63, 64, 199]
+    _check(y[:, cols].cpu().numpy(), x[:, cols].cpu().numpy(), h, orc)
 
 
 def test_million_channels_over_several_launch_windows(F):
