@@ -326,7 +326,10 @@ filark_status filark_ema_destroy(filark_ema_t st);
  *              overlap (neighbouring outputs read the same inputs).
  *              Asynchronous on `stream`; n_t = 0 is a no-op.  Successive
  *              calls must be ordered (one stream, or synchronised), since
- *              each reads the history the previous one wrote.
+ *              each reads the history the previous one wrote.  Which of the
+ *              state's two history buffers is current lives on the device,
+ *              so a call captured in a HIP graph carries the history from
+ *              replay to replay like an eager call.
  *   _state_get / _set  the history, host FP32 [n_taps - 1][n_ch], oldest row
  *              first (nothing when n_taps = 1).  Synchronous.
  * Errors: FILARK_EINVAL (arguments, overlap), FILARK_ESHAPE (n_ch mismatch),

@@ -229,8 +229,8 @@ struct filark_fir_state {
   int64_t n_ch = 0;
   int n_taps = 0, n_pad = 0;      // M and M padded to the tap chunk
   float *d_h = nullptr;           // [n_pad] FP32 taps, zero past M
-  float *d_hist[2] = {};          // [max(M - 1, 1)][n_ch] each; d_hist[cur] is current
-  int cur = 0;
+  float *d_hist[2] = {};          // [max(M - 1, 1)][n_ch] each; d_ctl[0] names the current one
+  uint32_t *d_ctl = nullptr;      // [2]: [0] & 1 names the current history buffer
   int rows = 0, waves = 1;        // output rows per wave (0: by launch), waves per workgroup
   int order = 2;                  // workgroup order: a channel slab per XCD, swept row block by row block
 };
@@ -1363,6 +1363,8 @@ filark_status filark_fir_init(filark_fir_t *out, const double *taps, int n_taps,
     e = hipMalloc(&st->d_hist[i], hist_bytes);
     if (e == hipSuccess) e = hipMemsetAsync(st->d_hist[i], 0, hist_bytes, stream);
   }
+  if (e == hipSuccess) e = hipMalloc(&st->d_ctl, 2 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemsetAsync(st->d_ctl, 0, 2 * sizeof(uint32_t), stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     filark_fir_destroy(st);
@@ -1408,8 +1410,9 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
   FirParams p;
   std::memset(&p, 0, sizeof p);
   p.h = st->d_h;
-  p.hin = st->d_hist[st->cur];
-  p.hout = st->d_hist[st->cur ^ 1];
+  p.hist0 = st->d_hist[0];
+  p.hist1 = st->d_hist[1];
+  p.ctl = st->d_ctl;
   p.n_ch = n_ch;
   p.hrange = (int32_t)(hm * rowb);
   p.hm = (int32_t)hm;
@@ -1446,9 +1449,9 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
     p.per_xcd = st->order == 2 ? (p.n_cg + 7) / 8 : (int32_t)((n_wg + 7) / 8);
     e = launch_fir(p, R, stream);
   }
+  if (e == hipSuccess) e = launch_fir_flip(st->d_ctl, stream);
   if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "launch failed: %s", hipGetErrorString(e));
-  st->cur ^= 1;
   return FILARK_OK;
 }
 
@@ -1456,7 +1459,9 @@ filark_status filark_fir_state_get(filark_fir_t st, float *hist, hipStream_t str
   if (!st || !hist) return fail(FILARK_EINVAL, "null pointer");
   if (st->n_taps == 1) return FILARK_OK;
   HIP_TRY(hipStreamSynchronize(stream));
-  HIP_TRY(hipMemcpy(hist, st->d_hist[st->cur], (size_t)(st->n_taps - 1) * st->n_ch * sizeof(float),
+  uint32_t ctl = 0;
+  HIP_TRY(hipMemcpy(&ctl, st->d_ctl, sizeof ctl, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(hist, st->d_hist[ctl & 1u], (size_t)(st->n_taps - 1) * st->n_ch * sizeof(float),
                     hipMemcpyDeviceToHost));
   return FILARK_OK;
 }
@@ -1468,7 +1473,9 @@ filark_status filark_fir_state_set(filark_fir_t st, const float *hist, hipStream
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(hist[i])) return fail(FILARK_EINVAL, "state_set: history must be finite");
   HIP_TRY(hipStreamSynchronize(stream));
-  HIP_TRY(hipMemcpy(st->d_hist[st->cur], hist, n * sizeof(float), hipMemcpyHostToDevice));
+  uint32_t ctl = 0;
+  HIP_TRY(hipMemcpy(&ctl, st->d_ctl, sizeof ctl, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(st->d_hist[ctl & 1u], hist, n * sizeof(float), hipMemcpyHostToDevice));
   return FILARK_OK;
 }
 
@@ -1477,6 +1484,7 @@ filark_status filark_fir_destroy(filark_fir_t st) {
   if (st->d_h) (void)hipFree(st->d_h);
   for (int i = 0; i < 2; ++i)
     if (st->d_hist[i]) (void)hipFree(st->d_hist[i]);
+  if (st->d_ctl) (void)hipFree(st->d_ctl);
   delete st;
   return FILARK_OK;
 }

@@ -18,8 +18,9 @@ struct FirParams {
   const float *x;    // chunk row lo = max(0, T0 - (Mp - 1)): base of the input reads
   float *y;          // chunk row T0
   const float *h;    // taps [Mp], FP32, zero past the filter length
-  const float *hin;  // carried history [M - 1][n_ch], oldest row first
-  float *hout;       // history after this chunk, same layout (a different buffer)
+  float *hist0, *hist1;  // history buffers [M - 1][n_ch], oldest row first: a call
+                         // reads the one ctl[0] names and writes the other
+  const uint32_t *ctl;   // [0] & 1: which buffer holds the history (flipped by launch_fir_flip)
   int64_t n_ch;
   int32_t xoff;       // T0 - lo: window row 0 sits xoff rows past the input base
   int32_t n_rows;     // rows in this window
@@ -30,7 +31,7 @@ struct FirParams {
   int32_t n_chunks;   // Mp / kFirChunk
   int32_t hs;         // window row where the new history starts: n_t - (M - 1) - T0
   int32_t hcopy;      // history rows carried over unchanged (chunks shorter than M - 1)
-  int32_t hsrc;       // first carried-over row of hin (n_t)
+  int32_t hsrc;       // first carried-over row of the history read (n_t)
   int32_t n_cg, n_tb;  // channel groups of 64, workgroups along the window's rows
   int32_t per_xcd, nw;
   int32_t chan_minor;  // workgroup order 0, 1 or 2 (fir_tile_of); for 2, per_xcd is the slab width in groups
@@ -40,5 +41,9 @@ struct FirParams {
 inline bool fir_rows_ok(int R) { return R == 16 || R == 32 || R == 48; }
 
 hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream);
+
+// Ends a call: the history buffer its launches wrote becomes the current one
+// (a one-lane kernel, so that graph replays alternate the buffers too).
+hipError_t launch_fir_flip(uint32_t *ctl, hipStream_t stream);
 
 }  // namespace filark

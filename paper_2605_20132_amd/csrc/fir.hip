@@ -29,6 +29,18 @@ typedef const FILARK_CONST float cfloat;
 typedef const FILARK_CONST FirParams *firparams_t;
 __device__ __forceinline__ firparams_t firparams() { return dev::kparams<FirParams>(); }
 
+// The history buffer a launch reads and the one it writes, by the parity in
+// ctl[0] (flipped by fir_flip_kernel after a call's last launch).
+struct Hist {
+  const float *in;
+  float *out;
+  uint32_t par;
+};
+__device__ __forceinline__ Hist fir_hist(firparams_t p) {
+  const uint32_t par = uniform((int)(*p->ctl & 1u));
+  return Hist{par ? p->hist1 : p->hist0, par ? p->hist0 : p->hist1, par};
+}
+
 // Channel group and row block of this workgroup; false past the grid's work.
 // Order 0: XCD x takes a contiguous run of (group, block) pairs, blocks
 // fastest.  Order 1: the same with groups fastest, so an XCD streams whole
@@ -59,10 +71,9 @@ __device__ __forceinline__ bool fir_tile_of(firparams_t p, int &cg, int &tb) {
 }
 
 template <int R>
-__global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
+__device__ __forceinline__ void fir_body(firparams_t p, const Hist &hh) {
   constexpr int KC = kFirChunk;
   constexpr int NX = R + KC - 1;  // input rows one tap chunk touches
-  firparams_t p = firparams();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x / kWave);
   int cg, tb;
@@ -96,7 +107,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
       // the chunk reaches back before the input: rows -(M - 1) .. -1 come from
       // the carried history, rows further back (zero taps only) read 0
       const __amdgpu_buffer_rsrc_t rx = rsrc(p->x, p->range);
-      const __amdgpu_buffer_rsrc_t rh = rsrc(p->hin, p->hrange);
+      const __amdgpu_buffer_rsrc_t rh = rsrc(hh.in, p->hrange);
       const int hm = p->hm;
 #pragma unroll
       for (int i = NX - 1; i >= 0; --i) {
@@ -111,7 +122,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
       // the wave's own rows (xw[KC - 1 + r]) that end the chunk become history
       const int hs = p->hs, n_rows = p->n_rows;
       if (t0 + R > hs) {
-        const __amdgpu_buffer_rsrc_t ro = rsrc(p->hout, p->hrange);
+        const __amdgpu_buffer_rsrc_t ro = rsrc(hh.out, p->hrange);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int t = t0 + r;
@@ -122,8 +133,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
       // a chunk shorter than M - 1 rows keeps the newest old history rows
       const int hcopy = p->hcopy;
       if (t0 == 0 && hcopy > 0) {
-        const __amdgpu_buffer_rsrc_t rh = rsrc(p->hin, p->hrange);
-        const __amdgpu_buffer_rsrc_t ro = rsrc(p->hout, p->hrange);
+        const __amdgpu_buffer_rsrc_t rh = rsrc(hh.in, p->hrange);
+        const __amdgpu_buffer_rsrc_t ro = rsrc(hh.out, p->hrange);
         const int src = p->hsrc;
         for (int j = 0; j < hcopy; ++j) {
           const float v = buf_ld(rh, cval ? (uint32_t)(src + j) * rowb + cb : kOffInvalid);
@@ -149,11 +160,19 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
   for (int r = 0; r < R; ++r) buf_st(ry, vy + (uint32_t)r * rb, acc[r]);
 }
 
+template <int R>
+__global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel(FirParams) {
+  firparams_t p = firparams();
+  const Hist hh = fir_hist(p);
+  fir_body<R>(p, hh);
+}
+
 // Input rows of the unrolled kernel by age: xr[j] is row t0 + R - 1 - j, so
 // output row t0 + r takes tap kk from xr[R - 1 - r + kk].  Slab s holds
 // xr[32 s .. 32 s + 31]; the rows before the input come from the history.
 template <int R, int N>
-__device__ __forceinline__ void fir_load_slab(firparams_t p, int t0, bool cval, uint32_t cb, int s, float (&xr)[N]) {
+__device__ __forceinline__ void fir_load_slab(firparams_t p, const float *hin, int t0, bool cval, uint32_t cb, int s,
+                                              float (&xr)[N]) {
   constexpr int KC = kFirChunk;
   const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
   const int umax = uniform(t0 + p->xoff + R - 1 - KC * s);  // base row of xr[32 s]
@@ -166,7 +185,7 @@ __device__ __forceinline__ void fir_load_slab(firparams_t p, int t0, bool cval, 
     for (int i = 0; i < KC; ++i)
       if (i < n) xr[KC * s + i] = buf_ld(rx, vo - (uint32_t)i * rb);
   } else {
-    const __amdgpu_buffer_rsrc_t rh = rsrc(p->hin, p->hrange);
+    const __amdgpu_buffer_rsrc_t rh = rsrc(hin, p->hrange);
     const int hm = p->hm;
 #pragma unroll
     for (int i = 0; i < KC; ++i) {
@@ -201,13 +220,13 @@ constexpr int fir_reach() {
 // Chunk Q of NCH: first half of its taps, then the next chunk's last slab
 // and taps are fetched, then the second half; the next chunk follows.
 template <int NCH, int Q, int R, int N>
-__device__ __forceinline__ void fir_chunk(firparams_t p, int t0, bool cval, uint32_t cb, float (&xr)[N],
-                                          float (&hk)[kFirChunk], float (&acc)[R]) {
+__device__ __forceinline__ void fir_chunk(firparams_t p, const float *hin, int t0, bool cval, uint32_t cb,
+                                          float (&xr)[N], float (&hk)[kFirChunk], float (&acc)[R]) {
   constexpr int KC = kFirChunk, S = Q + 1 + fir_reach<R>();
   fir_half<R, N, Q, 0>(hk, xr, acc);
   float hn[KC];
   __builtin_amdgcn_sched_barrier(0);
-  if constexpr (Q + 1 < NCH && KC * S < N) fir_load_slab<R>(p, t0, cval, cb, S, xr);
+  if constexpr (Q + 1 < NCH && KC * S < N) fir_load_slab<R>(p, hin, t0, cval, cb, S, xr);
   if constexpr (Q + 1 < NCH) {
     cfloat *hp = (cfloat *)p->h + KC * (Q + 1);
 #pragma unroll
@@ -218,7 +237,7 @@ __device__ __forceinline__ void fir_chunk(firparams_t p, int t0, bool cval, uint
   if constexpr (Q + 1 < NCH) {
 #pragma unroll
     for (int e = 0; e < KC; ++e) hk[e] = hn[e];
-    fir_chunk<NCH, Q + 1>(p, t0, cval, cb, xr, hk, acc);
+    fir_chunk<NCH, Q + 1>(p, hin, t0, cval, cb, xr, hk, acc);
   }
 }
 
@@ -228,9 +247,8 @@ __device__ __forceinline__ void fir_chunk(firparams_t p, int t0, bool cval, uint
 // halfway through a chunk, into the registers of rows that chunk no longer
 // needs, and the FMAs keep the ascending tap order (same bits as fir_kernel).
 template <int NCH, int R>
-__global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
+__device__ __forceinline__ void fir_body_u(firparams_t p, const Hist &hh) {
   constexpr int KC = kFirChunk, N = R + KC * NCH - 1;
-  firparams_t p = firparams();
   const int lane = threadIdx.x & (kWave - 1);
   const int w = uniform(threadIdx.x / kWave);
   int cg, tb;
@@ -244,12 +262,12 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
   float xr[N];
 #pragma unroll
   for (int s = 0; s <= fir_reach<R>(); ++s)
-    if (KC * s < N) fir_load_slab<R>(p, t0, cval, cb, s, xr);
+    if (KC * s < N) fir_load_slab<R>(p, hh.in, t0, cval, cb, s, xr);
   {
     const int hs = p->hs, n_rows = p->n_rows;
     if (t0 + R > hs) {
       const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
-      const __amdgpu_buffer_rsrc_t ro = rsrc(p->hout, p->hrange);
+      const __amdgpu_buffer_rsrc_t ro = rsrc(hh.out, p->hrange);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int t = t0 + r;
@@ -260,8 +278,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
     const int hcopy = p->hcopy;
     if (t0 == 0 && hcopy > 0) {
       const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
-      const __amdgpu_buffer_rsrc_t rh = rsrc(p->hin, p->hrange);
-      const __amdgpu_buffer_rsrc_t ro = rsrc(p->hout, p->hrange);
+      const __amdgpu_buffer_rsrc_t rh = rsrc(hh.in, p->hrange);
+      const __amdgpu_buffer_rsrc_t ro = rsrc(hh.out, p->hrange);
       const int src = p->hsrc;
       for (int j = 0; j < hcopy; ++j) {
         const float v = buf_ld(rh, cval ? (uint32_t)(src + j) * rb + cb : kOffInvalid);
@@ -279,13 +297,34 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) fir_kernel_u(FirParams) {
 #pragma unroll
     for (int k = 0; k < KC; ++k) hk[k] = hp[k];
   }
-  fir_chunk<NCH, 0>(p, t0, cval, cb, xr, hk, acc);
+  fir_chunk<NCH, 0>(p, hh.in, t0, cval, cb, xr, hk, acc);
 
   const uint32_t rb = fresh((uint32_t)p->n_ch * 4u);
   const __amdgpu_buffer_rsrc_t ry = rsrc(p->y, p->out_range);
   const uint32_t vy = cval ? (uint32_t)t0 * rb + cb : kOffInvalid;
 #pragma unroll
   for (int r = 0; r < R; ++r) buf_st(ry, vy + (uint32_t)r * rb, acc[r]);
+}
+
+// Waves per SIMD the unrolled kernel is held to (its register budget):
+// 4 (128 VGPRs) at 32 rows, 3 (168) at 48.
+template <int R>
+constexpr int fir_waves_per_eu() {
+  return R == 32 ? 4 : 3;
+}
+
+template <int NCH, int R>
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(fir_waves_per_eu<R>())))
+fir_kernel_u(FirParams) {
+  firparams_t p = firparams();
+  const Hist hh = fir_hist(p);
+  fir_body_u<NCH, R>(p, hh);
+}
+
+// After a call's last launch: the history it wrote becomes the current one.
+// One lane; a vector load and store.
+__global__ void __launch_bounds__(kWave) fir_flip_kernel(uint32_t *ctl) {
+  if (threadIdx.x == 0) ctl[0] ^= 1u;
 }
 
 // The kernel a launch with R rows per wave and n_chunks tap chunks runs.
@@ -316,9 +355,15 @@ hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream) {
   // unrolled up to 64 taps; beyond, its live rows would cost occupancy
   const void *k = fir_kernel_for(R, p.n_chunks);
   if (!k) return hipErrorInvalidValue;
-  void *args[] = {const_cast<FirParams *>(&p)};
+  FirParams q = p;
+  void *args[] = {&q};
   const hipError_t e = hipLaunchKernel(k, grid, block, args, 0, stream);
   if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_fir_flip(uint32_t *ctl, hipStream_t stream) {
+  hipLaunchKernelGGL(fir_flip_kernel, dim3(1), dim3(kWave), 0, stream, ctl);
   return hipGetLastError();
 }
 

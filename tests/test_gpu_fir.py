@@ -166,6 +166,40 @@ def test_orders_on_few_channel_groups(F, order):
         _check(y.cpu().numpy(), x.cpu().numpy(), h, orc)
 
 
+@pytest.mark.parametrize("M,n_ch,chunk", [(64, 300, 500), (101, 70, 40), (33, 65, 1)])
+def test_graph_replays_carry_history(F, M, n_ch, chunk):
+    """One call captured in a HIP graph, replayed over successive chunks with
+    eager work in between: every replay equals an eager object's call on the
+    same chunk bit for bit, and the carried history follows (chunks shorter
+    than the history included)."""
+    h = _taps(M, "random", 21)
+    g0 = torch.Generator(device="cuda").manual_seed(22)
+    x = torch.randn((6 * chunk, n_ch), generator=g0, device="cuda", dtype=torch.float32)
+    f, ref = F.Fir(h, n_ch), F.Fir(h, n_ch)
+    xs, ys = torch.empty((chunk, n_ch), device="cuda"), torch.empty((chunk, n_ch), device="cuda")
+    xs.copy_(x[:chunk])
+    f.process(xs, ys)  # warm-up outside the capture
+    r0 = ref.process(x[:chunk].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(ys, r0)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            f.process(xs, ys, stream=s)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(f.get_state(), ref.get_state())  # the capture ran nothing
+    for i in range(1, 6):
+        xs.copy_(x[i * chunk:(i + 1) * chunk])
+        g.replay()
+        r = ref.process(x[i * chunk:(i + 1) * chunk].contiguous())
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        assert torch.equal(ys, r), f"replay {i}"
+        np.testing.assert_array_equal(f.get_state(), ref.get_state())
+
+
 def test_state_set_continues_a_stream(F):
     orc = _orc()
     n_ch, M = 70, 40
