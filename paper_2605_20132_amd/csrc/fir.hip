@@ -34,11 +34,10 @@ __device__ __forceinline__ firparams_t firparams() { return dev::kparams<FirPara
 struct Hist {
   const float *in;
   float *out;
-  uint32_t par;
 };
 __device__ __forceinline__ Hist fir_hist(firparams_t p) {
   const uint32_t par = uniform((int)(*p->ctl & 1u));
-  return Hist{par ? p->hist1 : p->hist0, par ? p->hist0 : p->hist1, par};
+  return Hist{par ? p->hist1 : p->hist0, par ? p->hist0 : p->hist1};
 }
 
 // Channel group and row block of this workgroup; false past the grid's work.
