@@ -541,8 +541,9 @@ def main():
                     help="also run one plain device copy of 512 MiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the channel-sharded multi-GPU layout is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(channels would shard across GPUs with no communication in the forward pass; "
+                                   "no multi-GPU launch is implemented)"}))
         sys.exit(2)
 
     import torch
