@@ -312,8 +312,10 @@ filark_status filark_ema_destroy(filark_ema_t st);
  * on the GPU the two agree bit for bit (every output takes its taps in
  * ascending order in FP32 FMAs).
  *   _init      taps: host FP64 [n_taps], finite, applied as FP32;
- *              1 <= n_taps <= 1024; n_ch in [1, 2^24] (and small enough that
- *              (n_taps + 100) rows of n_ch floats stay below 2 GiB).
+ *              1 <= n_taps <= 1024; n_ch in [1, 2^24], and small enough
+ *              that 2 Mp + 81 + 96 w rows of n_ch floats stay below 2 GiB
+ *              (Mp: n_taps rounded up to 32; w: waves per workgroup, 1 by
+ *              default; checked at _init and _set_tile).
  *   _set_tile  output rows per wave (0: 48 for launch windows of 8192 rows
  *              or more with at most 64 taps, else 32; or 16, 32, 48), waves
  *              per workgroup (1..8)
