@@ -107,6 +107,9 @@ def test_null_and_range_errors_without_gpu(F):
     assert L.filark_fir_init(ctypes.byref(h), taps.ctypes.data_as(D), 4, 0, vp(0)) == F.EINVAL
     assert L.filark_fir_init(ctypes.byref(h), None, 4, 4, vp(0)) == F.EINVAL
     assert L.filark_fir_init(None, taps.ctypes.data_as(D), 4, 4, vp(0)) == F.EINVAL
+    # one channel past the launch-window limit for 64 taps (2 x 64 + 81 + 96 rows
+    # of n_ch floats must stay below 2 GiB): refused before any allocation
+    assert L.filark_fir_init(ctypes.byref(h), np.ones(64).ctypes.data_as(D), 64, 1_760_233, vp(0)) == F.EINVAL
     assert L.filark_fir_process(vp(0), vp(0), vp(0), 4, 4, vp(0)) == F.EINVAL
     assert L.filark_fir_set_tile(vp(0), 32, 4, 0) == F.EINVAL
     assert L.filark_fir_state_get(vp(0), vp(0), vp(0)) == F.EINVAL

@@ -256,6 +256,26 @@ def test_long_window_default_tile_matches_fixed_tiles(F, M):
     _check(y[:, cols].cpu().numpy(), x[:, cols].cpu().numpy(), h, orc)
 
 
+def test_channel_limit_for_64_taps(F):
+    """The largest channel count 64 taps allow (launch windows of 96 rows):
+    a 100-row record in two chunks against the oracle on sampled channels."""
+    orc = _orc()
+    n_ch, M = 1_760_232, 64
+    h = _taps(M, "sinc", 5)
+    g = torch.Generator(device="cuda").manual_seed(14)
+    x = torch.randn((100, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    f = F.Fir(h, n_ch)
+    y = torch.cat([f.process(x[:30].contiguous()), f.process(x[30:].contiguous())])
+    torch.cuda.synchronize()
+    cols = np.array([0, 64, n_ch // 2, n_ch - 1])
+    idx = torch.from_numpy(cols).cuda()
+    _check(y.index_select(1, idx).cpu().numpy(), x.index_select(1, idx).cpu().numpy(), h, orc)
+    with pytest.raises(F.FilarkError):
+        f.set_tile(32, 2, 2)  # a second wave per workgroup needs 96 rows more
+    del x, y
+    torch.cuda.empty_cache()
+
+
 def test_million_channels_over_several_launch_windows(F):
     """1,000,003 channels x 700 rows in two chunks: every launch window is a
     few hundred rows, so windows meet inside both chunks; sampled channels
