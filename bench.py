@@ -454,14 +454,14 @@ def batched_leg(F, torch, dev, replays: int, parity: bool):
     from paper_2605_20132_amd.autotune import Autotuner
 
     specs = synth.draw_batched_streams()
-    tuner = Autotuner(None, block=48, waves=4, reps=3)
+    tuner = Autotuner(None, block=64, waves=4, reps=3)
     sts, xs, ys, soss = [], [], [], []
     for sp in specs:
         sos = F.sos_design(sp.order, "bandpass", sp.f1, sp.f2, sp.fs)
         x = synth.pink_noise(sp.n_t, sp.n_ch, seed=sp.seed, device=dev)
         grp = tuner.group_for(sos, sp.n_ch, sp.n_t)
         st = F.SOSState(sos, sp.n_ch)
-        st.set_tile(64, 4, grp)
+        st.set_tile(tuner.block, tuner.waves, grp)  # the tile the tuner measured
         sts.append(st)
         xs.append(x)
         ys.append(torch.empty_like(x))
@@ -522,6 +522,63 @@ def batched_leg(F, torch, dev, replays: int, parity: bool):
     return res
 
 
+def extras(args, torch, dev, F, st, sl, step, x, y, cf, chunk, n_chunks, n_t, n_ch, stream, e0, e1):
+    """Event pair per launch, graph replay of a step and the on-box copy bandwidth."""
+    # ---- the same, with an event pair around each launch (adds the event
+    # overhead to every launch; reported beside the figure above)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(n_chunks)]
+    torch.cuda._sleep(200_000_000)  # back the queue up so host launch latency is not timed
+    for i in range(n_chunks):
+        a, b = i * chunk, min(n_t, (i + 1) * chunk)
+        evs[i][0].record(stream)
+        F.sos_stalta_process(st, sl, x[a:b], y[a:b], cf[a:b], write_y=True, stream=stream)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    full = [evs[i][0].elapsed_time(evs[i][1]) for i in range(n_chunks) if (i + 1) * chunk <= n_t]
+    pair_ms = float(np.mean(full))
+    log(f"[bench] kernel avg {pair_ms * 1e3:.1f} us/launch with an event pair per launch")
+
+    # ---- the same 60 launches captured in one graph
+    graph = None
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step(st, sl)
+        torch.cuda.synchronize()
+        for _ in range(2):
+            g.replay()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / args.steps
+        st.check()
+        graph = {"ms_per_step": gms, "value": n_ch * n_t / (gms / 1e3)}
+        log(f"[bench] graph replay {gms:.3f} ms/step -> {graph['value']:.3e} ch-samples/s")
+    except Exception as e:  # capture is an optional extra measurement
+        log(f"[bench] graph capture unavailable: {e}")
+
+    if args.calib_copy:
+        src = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        flush = torch.empty(256 << 20, dtype=torch.float32, device=dev)
+        flush.fill_(2.0)  # 1 GiB written after src: src is not cache resident when copied
+        del flush
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
+        del src, dst
+
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"[bench] on-box device copy {copy_gbs:.0f} GB/s (read + write)")
+    return pair_ms, graph, copy_gbs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -537,9 +594,15 @@ def main():
     ap.add_argument("--no-fir", action="store_true")
     ap.add_argument("--n-ch", type=int, default=6000)
     ap.add_argument("--n-t", type=int, default=90_000)
+    ap.add_argument("--profile", action="store_true",
+                    help="only the timed launches of each leg run (no parity passes, event pairs, graph replays, "
+                         "copy or CPU timing), so a kernel trace averages exactly the launches the bench times")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of 512 MiB (counter calibration for profiles)")
     args = ap.parse_args()
+    if args.profile:
+        args.no_parity = True
+        args.no_cpu = True
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
                                    "(channels would shard across GPUs with no communication in the forward pass; "
@@ -577,10 +640,11 @@ def main():
 
     # ---- parity of one full pass from the zero state (sampled channels)
     st, sl = make_states()
-    step(st, sl)
-    torch.cuda.synchronize()
-    st.check()
-    sl.check()
+    if not args.profile:
+        step(st, sl)
+        torch.cuda.synchronize()
+        st.check()
+        sl.check()
     parity = None
     if not args.no_parity:
         import oracle
@@ -637,58 +701,10 @@ def main():
     achieved = bytes_launch / (kern_ms / 1e3) / 1e9
     log(f"[bench] kernel avg {kern_ms * 1e3:.1f} us/launch over the timed region -> {achieved:.0f} GB/s algorithmic")
 
-    # ---- the same, with an event pair around each launch (adds the event
-    # overhead to every launch; reported beside the figure above)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(n_chunks)]
-    torch.cuda._sleep(200_000_000)  # back the queue up so host launch latency is not timed
-    for i in range(n_chunks):
-        a, b = i * chunk, min(n_t, (i + 1) * chunk)
-        evs[i][0].record(stream)
-        F.sos_stalta_process(st, sl, x[a:b], y[a:b], cf[a:b], write_y=True, stream=stream)
-        evs[i][1].record(stream)
-    torch.cuda.synchronize()
-    full = [evs[i][0].elapsed_time(evs[i][1]) for i in range(n_chunks) if (i + 1) * chunk <= n_t]
-    pair_ms = float(np.mean(full))
-    log(f"[bench] kernel avg {pair_ms * 1e3:.1f} us/launch with an event pair per launch")
-
-    # ---- the same 60 launches captured in one graph
-    graph = None
-    try:
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            step(st, sl)
-        torch.cuda.synchronize()
-        for _ in range(2):
-            g.replay()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.steps):
-            g.replay()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        gms = e0.elapsed_time(e1) / args.steps
-        st.check()
-        graph = {"ms_per_step": gms, "value": n_ch * n_t / (gms / 1e3)}
-        log(f"[bench] graph replay {gms:.3f} ms/step -> {graph['value']:.3e} ch-samples/s")
-    except Exception as e:  # capture is an optional extra measurement
-        log(f"[bench] graph capture unavailable: {e}")
-
-    if args.calib_copy:
-        src = torch.empty(128 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        flush = torch.empty(256 << 20, dtype=torch.float32, device=dev)
-        flush.fill_(2.0)  # 1 GiB written after src: src is not cache resident when copied
-        del flush
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
-        del src, dst
-
-    copy_gbs = copy_bandwidth(torch, dev)
-    log(f"[bench] on-box device copy {copy_gbs:.0f} GB/s (read + write)")
+    pair_ms, graph, copy_gbs = None, None, None
+    if not args.profile:
+        pair_ms, graph, copy_gbs = extras(args, torch, dev, F, st, sl, step, x, y, cf, chunk, n_chunks, n_t, n_ch,
+                                          stream, e0, e1)
 
     batched = None
     if not args.no_batched:
@@ -719,10 +735,10 @@ def main():
     if t is not None:
         traffic = t["hbm_bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "copy_peak": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                "copy_peak": copy_gbs, "frac_of_copy": achieved / copy_gbs if copy_gbs else None,
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": "fwd_kernel<K=4,stalta,write_y>", "kernel_us": kern_ms * 1e3,
-                "kernel_us_event_pairs": pair_ms * 1e3,
+                "kernel_us_event_pairs": pair_ms * 1e3 if pair_ms is not None else None,
                 "algorithmic_bytes_per_launch": bytes_launch}
 
     cpu = None

@@ -8,11 +8,11 @@
  * split of a record into chunks gives the output of a single call over the
  * whole record.  The first chunk after initialisation carries the start-up
  * transient set by the zero initial condition; later chunks carry none
- * (Section 5.2, "Signal processing performance").
+ * (Section 6.2, "Signal processing performance").
  *
  * Data layout (every entry point): records are FP32, time-major
  * [n_t][n_ch] with row stride n_ch (channel contiguous), the 'nt_nc'
- * convention of the paper's binary tape (Section 3.6).
+ * convention of the paper's binary tape (Section 3.5).
  *
  * Ownership: the caller owns every data buffer (device memory for signals,
  * host memory for coefficients and state snapshots).  The library owns its
@@ -141,7 +141,7 @@ filark_status filark_stalta_init(filark_stalta_t *st, double sta_s, double lta_s
 
 /*
  * Zero-phase (forward-backward) SOS filtering of a window: the "zero-phase"
- * option of the display filter of Section 3.4 (a non-causal filter of a whole
+ * option of the display filter of Section 3.2 (a non-causal filter of a whole
  * window, not a stream).  The cascade runs forward over in[0 .. n_t) from
  * rest, then backward in time over that output from rest, so the magnitude
  * response is |H|^2 and the phase is zero; no edge padding is added.  Uses
@@ -254,7 +254,12 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
  *   _bind    records one chunk per stream: in[s], out[s] device FP32
  *            [n_t[s]][n_ch of state s] (host arrays of device pointers;
  *            n_t[s] = 0 skips the stream), builds the work tables and uploads
- *            them (synchronous).  Rebind when pointers or lengths change.
+ *            them (synchronous).  Rebind when pointers or lengths change,
+ *            and after filark_tile_set on any of the states (a launch after
+ *            such a change fails with FILARK_EINVAL; bind refuses a state
+ *            whose block or waves differ from the batch's).  A graph holding
+ *            an earlier launch must be captured again after a bind: the
+ *            work tables it names may have been reallocated.
  *   _launch  enqueues the bound work on `stream`: a fill kernel that clears
  *            the completion stamps, then one kernel per (window round,
  *            section count), each covering every stream of that kind.  The

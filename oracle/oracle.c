@@ -8,7 +8,7 @@
  * out from their textbook definitions, one plain loop at a time.
  *
  * What it computes (the paper, Section 3.4 "Signal processing, pipelines,
- * and algorithm integration", and its performance Section 5.2):
+ * and algorithm integration", and its performance Section 6.2):
  *   - stateful-compatible causal IIR filtering in second-order sections: a
  *     chunk goes in, an output of the same length comes out and the filter
  *     state is carried to the next call, so that a chunked run equals a
@@ -27,7 +27,7 @@
  * are listed, with every other reading, in the design notes.
  *
  * Layout: records are time-major x[t * n_ch + c] (channel contiguous), the
- * paper's 'nt_nc' tape convention (Section 3.6).  Arithmetic is IEEE double,
+ * paper's 'nt_nc' tape convention (Section 3.5).  Arithmetic is IEEE double,
  * built without fast-math and without FMA contraction.
  */
 #include <complex.h>
@@ -601,7 +601,7 @@ int64_t oracle_trigger(const float *cf, int64_t n_ch, int64_t n_t, float on, flo
 
 /* ------------------------------------------------------------------------
  * Zero-phase filtering of a window (the display filter's zero-phase option,
- * Section 3.4): the cascade from rest forward over x, then from rest over the
+ * Section 3.2): the cascade from rest forward over x, then from rest over the
  * result taken backward in time; no padding at either edge.  x and y may be
  * the same array.
  * ------------------------------------------------------------------------ */

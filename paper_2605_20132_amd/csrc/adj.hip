@@ -24,7 +24,10 @@
 // its block from the exact end state.  The forward values the backward pass
 // needs (section outputs, the STA/LTA averages) are recomputed from the
 // window's checkpointed start state with the forward scan of fwd.hip; the
-// averages are walked backwards from their block-end values.
+// averages are then run forward over each block from their exact entry
+// values, and every row keeps the two terms it adds to the adjoints of
+// (sta, lta), so the backward passes never divide by a decay (which is 0 for
+// a one-sample window).
 //
 // Lanes past the window's last row, or past the last channel, hold zeros and
 // contribute nothing.  Coefficient gradients are summed in FP64 per lane, then
@@ -67,28 +70,40 @@ __device__ __forceinline__ double recip(double v) {
   return fma(r, fma(-v, r, 1.0), r);
 }
 
-// Backward step of the STA/LTA at one row: (A, B) -> adjoints before the row,
-// (S, Lg) -> the scaled sums before the row; returns ybar of the row.
-struct SlBack {
-  double cs, cl, asd, ald, ias, ial, scale;
+// STA/LTA at one row, forward: the scaled sums (S, Lg) advance over e = y^2,
+// and the row's contributions to the adjoints of (sta, lta) are returned:
+// alpha = q / lta and beta = q cf / lta, with q = dL/dcf where cf is live
+// (else 0).  gq is dL/dcf (mode 0) or the target cf (mode 1).
+struct SlFwd {
+  double cs, cl, asd, ald, scale;
   int64_t nlta;
   int mode;
-  __device__ __forceinline__ double step(double &A, double &B, double &S, double &Lg, double yd,
-                                         double gq, int64_t gidx) const {
+  __device__ __forceinline__ void step(double &S, double &Lg, double yd, double gq, int64_t gidx, float &alpha,
+                                       float &beta) const {
+    const double e = yd * yd;
+    S = fma(asd, S, e);
+    Lg = fma(ald, Lg, e);
     const double sta = S * cs, lta = Lg * cl;
     const bool live = gidx >= nlta && lta > 0.0;
     const double rl = live ? recip(lta) : 0.0;
     const double cf = sta * rl;
     const double q = live ? (mode ? 2.0 * scale * (cf - gq) : gq) : 0.0;
-    const double Sb = fma(q, rl, A);
-    const double Lb = fma(-q * cf, rl, B);
-    const double e = yd * yd;
-    const double ybar = 2.0 * yd * fma(cs, Sb, cl * Lb);
+    const double a = q * rl;
+    alpha = (float)a;
+    beta = (float)(a * cf);
+  }
+};
+
+// STA/LTA at one row, backward: (A, B), the adjoints of (sta, lta) after the
+// row, become the adjoints before it; returns dL/dy of the row.
+struct SlBack {
+  double cs, cl, asd, ald;
+  __device__ __forceinline__ double step(double &A, double &B, double yd, float alpha, float beta) const {
+    const double Sb = A + (double)alpha;
+    const double Lb = B - (double)beta;
     A = asd * Sb;
     B = ald * Lb;
-    S = (S - e) * ias;
-    Lg = (Lg - e) * ial;
-    return ybar;
+    return 2.0 * yd * fma(cs, Sb, cl * Lb);
   }
 };
 
@@ -217,9 +232,9 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     }
   }
 
-  // ---------------- forward recompute: STA/LTA sums at block ends ----------------
+  // ---------------- forward recompute: STA/LTA sums at block starts ----------------
   int64_t g0 = 0;
-  double Se, Le;  // scaled sums after the block's last valid row
+  double Sin, Lin;  // scaled sums before the block's first row
   {
     aparams_t q = aparams();
     double S0 = 0.0, L0 = 0.0;
@@ -250,35 +265,47 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     xsl[2 * my] = s;
     xsl[2 * my + 1] = l;
     lds_barrier();
-    double Sin = S0, Lin = L0;
+    Sin = S0;
+    Lin = L0;
     if (b > 0) {
       Sin = xsl[2 * (my - CW)];
       Lin = xsl[2 * (my - CW) + 1];
     }
     lds_barrier();
-    // through this block's nv valid rows (fewer than L only at the window end)
-    cdouble *rp = as_const(q->dpow) + 2 * (q->n_lev + nv);
-    Se = fma(rp[0], Sin, s_loc);
-    Le = fma(rp[1], Lin, l_loc);
+  }
+
+  // ---------------- STA/LTA: per-row adjoint terms, forward ----------------
+  // gv[j] (dL/dcf or the target) is replaced by alpha, bt[j] holds beta
+  float bt[L];
+  {
+    aparams_t q = aparams();
+    const SlFwd sf{q->cs, q->cl, q->asd, q->ald, q->scale, q->nlta, q->mode};
+    double S = Sin, Lg = Lin;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      float al = 0.0f, be = 0.0f;
+      if (j < nv) sf.step(S, Lg, widen<3>(yk[K - 1][j]), widen<4>(gv[j]), g0 + row0 + j, al, be);
+      gv[j] = al;
+      bt[j] = be;
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 
   // ---------------- adjoint: STA/LTA ----------------
-  float yb[L];  // dL/dy of the cascade output at each row
+  float *yb = gv;  // dL/dy of the cascade output at each row, over alpha as it is consumed
   {
     aparams_t q = aparams();
-    SlBack sb{q->cs, q->cl, q->asd, q->ald, q->ias, q->ial, q->scale, q->nlta, q->mode};
+    const SlBack sb{q->cs, q->cl, q->asd, q->ald};
     double A = 0.0, B = 0.0;
     if (b == b_end && cval) {
       A = q->adj[NS * n_ch + c];
       B = q->adj[(NS + 1) * n_ch + c];
     }
-    {  // from the block end to its start, from zero (or the handed-in state)
-      double S = Se, Lg = Le;
+    // from the block end to its start, from zero (or the handed-in state)
 #pragma unroll
-      for (int j = L - 1; j >= 0; --j) {
-        if (j < nv) sb.step(A, B, S, Lg, widen<3>(yk[K - 1][j]), widen<4>(gv[j]), g0 + row0 + j);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+    for (int j = L - 1; j >= 0; --j) {
+      if (j < nv) (void)sb.step(A, B, widen<5>(yk[K - 1][j]), gv[j], bt[j]);
+      __builtin_amdgcn_sched_barrier(0);
     }
     cdouble *dp = as_const(q->dpow);
     int lev = 0;
@@ -306,11 +333,10 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       Bx = q->adj[(NS + 1) * n_ch + c];
     }
     lds_barrier();
-    double S = Se, Lg = Le;
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
       float v = 0.0f;
-      if (j < nv) v = (float)sb.step(Ax, Bx, S, Lg, widen<5>(yk[K - 1][j]), widen<6>(gv[j]), g0 + row0 + j);
+      if (j < nv) v = (float)sb.step(Ax, Bx, widen<6>(yk[K - 1][j]), gv[j], bt[j]);
       yb[j] = v;
       __builtin_amdgcn_sched_barrier(0);
     }

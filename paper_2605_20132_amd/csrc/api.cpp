@@ -175,6 +175,7 @@ struct filark_sos_state {
   double *d_state = nullptr;  // [2K][n_ch]
   Tables fwd;                 // forward kernel
   Tables adj;                 // adjoint kernel
+  uint64_t gen = 0;           // bumped whenever the forward tables are rebuilt
   // adjoint workspace: window checkpoints and per-group coefficient sums
   double *d_ck = nullptr;
   size_t ck_bytes = 0;
@@ -197,6 +198,7 @@ struct filark_stalta_state {
 struct filark_batch {
   int device = 0;
   std::vector<filark_sos_state *> st;
+  std::vector<uint64_t> gen;  // each state's table generation when bound
   int L = 0, nw = 0;
   FwdParams *d_descs = nullptr;
   size_t descs_bytes = 0;
@@ -529,7 +531,8 @@ filark_status filark_stalta_init(filark_stalta_t *out, double sta_s, double lta_
       !std::isfinite(fs * lta_s))
     return fail(FILARK_EINVAL, "windows and fs must be positive and finite");
   const double ns = std::round(sta_s * fs), nl = std::round(lta_s * fs);
-  if (ns < 1.0 || nl < 1.0 || nl > 9.0e15) return fail(FILARK_EINVAL, "window lengths must round to >= 1 sample");
+  if (ns < 1.0 || nl < 1.0 || ns > 9.0e15 || nl > 9.0e15)
+    return fail(FILARK_EINVAL, "window lengths must round to 1 .. 9e15 samples");
   if (n_ch < 1 || n_ch > (int64_t)1 << 24) return fail(FILARK_EINVAL, "n_ch must be in [1, 2^24]");
   filark_stalta_state *st = new (std::nothrow) filark_stalta_state();
   if (!st) return fail(FILARK_ENOMEM, "host allocation failed");
@@ -704,6 +707,7 @@ filark_status filark_tile_set(void *obj, int kind, int block, int waves, int gro
     if (tb.tile == t) return FILARK_OK;
     HIP_TRY(hipStreamSynchronize(stream));
     tb.tile = t;
+    if (!adjoint) ++st->gen;  // batches bound to this state must be bound again
     return sos_tables(st->cas, tb, stream);
   }
   if (kind == FILARK_STATE_STALTA || kind == FILARK_TILE_STALTA_ADJOINT) {
@@ -860,8 +864,6 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
   p.cl = 1.0 / (double)sl->nlta;
   p.asd = 1.0 - p.cs;
   p.ald = 1.0 - p.cl;
-  p.ias = 1.0 / p.asd;
-  p.ial = 1.0 / p.ald;
   p.nlta = sl->nlta;
   const uint64_t rowb = (uint64_t)n_ch * 4u;
   for (int64_t w = n_win - 1; w >= 0 && e == hipSuccess; --w) {
@@ -934,6 +936,9 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
   for (int s = 0; s < n; ++s) {
     filark_sos_state *st = b->st[s];
     const Tile &t = st->fwd.tile;
+    if (t.block != b->L || t.waves != b->nw)
+      return fail(FILARK_EINVAL, "stream %d: block %d and waves %d differ from the batch's %d and %d", s, t.block,
+                  t.waves, b->L, b->nw);
     if (n_t[s] < 0) return fail(FILARK_EINVAL, "stream %d: negative n_t", s);
     if (n_t[s] > 0 && (!in[s] || !out[s])) return fail(FILARK_EINVAL, "stream %d: null pointer", s);
     const int64_t rows = launch_rows(t, st->n_ch);
@@ -1004,6 +1009,8 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
   if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
   if (rc != FILARK_OK) return rc;
   if (e != hipSuccess) return fail(FILARK_EHIP, "batch upload: %s", hipGetErrorString(e));
+  b->gen.resize(n);
+  for (int s = 0; s < n; ++s) b->gen[s] = b->st[s]->gen;
   b->bound = true;
   return FILARK_OK;
 }
@@ -1011,6 +1018,9 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
 filark_status filark_batch_launch(filark_batch_t b, hipStream_t stream) {
   if (!b) return fail(FILARK_EINVAL, "null batch");
   if (!b->bound) return fail(FILARK_EINVAL, "batch not bound (filark_batch_bind)");
+  for (size_t s = 0; s < b->st.size(); ++s)
+    if (b->st[s]->gen != b->gen[s])
+      return fail(FILARK_EINVAL, "stream %zu: tile changed since filark_batch_bind; bind again", s);
   const int prev_dev = current_device();
   if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
   hipError_t e = launch_stamp_reset(b->d_stamps, (int)b->st.size(), stream);

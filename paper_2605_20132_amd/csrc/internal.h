@@ -70,7 +70,6 @@ struct AdjParams {
   const double *coef, *G, *Pw;  // forward tables (as FwdParams)
   const double *dpow;           // [n_lev][2] decays^(L 2^k), then [L + 1][2] decays^m
   double asd, ald;     // 1 - 1/nsta, 1 - 1/nlta
-  double ias, ial;     // 1 / asd, 1 / ald
   double cs, cl;       // 1/nsta, 1/nlta
   int64_t nlta;
 };

@@ -2,7 +2,7 @@
 
 Layout: every record is a ``torch.float32`` tensor of shape ``[n_t, n_ch]``
 (time-major, channel contiguous), the ``dims='nt_nc'`` convention of the
-paper's binary tape (Section 3.6, streaming-aware I/O).
+paper's binary tape (Section 3.5, streaming-aware I/O).
 
 The paper measures its causal IIR on ocean-cable DAS files that are not
 available here; these generators stand in for them with the shapes and

@@ -42,24 +42,3 @@ def gpu_available() -> bool:
         return torch.cuda.is_available()
     except Exception:
         return False
-
-
-def assert_within_ulps(a, b, ulps: int = 2, max_fraction: float = 1e-3, floor_rel: float = 1e-10):
-    """FP32 arrays [n_t, n_ch] equal up to `ulps` units in the last place, with
-    differing elements rare.  This is the run-to-run spread of the FP64 carry:
-    its rounding depends on which predecessor records a segment composed, so
-    two runs differ by FP64 rounding of the state, i.e. by ~1e-13 of the
-    channel's scale in the output.  Near a zero crossing that is many ulps of
-    the sample itself, so each channel also gets an absolute allowance of
-    `floor_rel` times its largest magnitude (still far below one FP32 ulp of
-    the channel's typical sample)."""
-    a = np.asarray(a, dtype=np.float32)
-    b = np.asarray(b, dtype=np.float32)
-    assert a.shape == b.shape
-    ulp = np.spacing(np.maximum(np.abs(a), np.abs(b))).astype(np.float64)
-    d = np.abs(a.astype(np.float64) - b.astype(np.float64))
-    scale = np.max(np.abs(a.astype(np.float64)), axis=0, keepdims=True) if a.ndim == 2 and a.size \
-        else np.max(np.abs(a.astype(np.float64)), initial=0.0)
-    bound = ulps * ulp + floor_rel * scale
-    assert np.all(d <= bound), float(np.max(d / bound))
-    assert np.mean(d > 0) <= max_fraction

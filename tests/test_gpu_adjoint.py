@@ -91,14 +91,14 @@ def _grad_mode_oracle(orc, sos, x, gcf, nsta, nlta, zi0, st0, g0, adj_in):
     return orc.stalta_grad(sos, x, tgt, nsta, nlta, 1.0, zi0, st0, g0, adj_in)
 
 
-def _check(gx, adj, gs, ogx, oadj, ogs, tol=1e-5):
+def _check(gx, adj, gs, ogx, oadj, ogs, tol=1e-5, tol_state=1e-6):
     ex = max_rel_rms(gx, ogx)
     es = float(np.linalg.norm(gs - ogs) / np.linalg.norm(ogs))
     ea = float(np.max(np.abs(adj - oadj)) / np.max(np.abs(oadj)))
     print(f"dL/dx rel-RMS {ex:.2e}  dL/dtheta rel-L2 {es:.2e}  adjoint state {ea:.2e}")
     assert ex <= tol
     assert es <= tol
-    assert ea <= 1e-6
+    assert ea <= tol_state
 
 
 @pytest.mark.parametrize("mode", ["grad", "mse"])
@@ -144,17 +144,16 @@ def test_adjoint_short_and_warmup_chunks(F):
         _check(*_chunk_case(F, 9, n_pre, n_t, sos, 20, 200, 24 + n_t, "mse"))
 
 
-def test_chunked_adjoint_chain_equals_oracle_one_shot(F):
-    """Forward with device checkpoints, then the chunks last to first,
-    carrying the adjoint state: the one-shot reference gradient."""
+def _chain_case(F, n_ch, nsta, nlta, splits, seed, raw=False):
+    """Forward with device checkpoints over the splits, then the chunks last
+    to first carrying the adjoint state, against the one-shot reference."""
     orc = _orc()
-    n_ch, nsta, nlta = 24, 30, 300
     sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
-    g = torch.Generator(device="cuda").manual_seed(31)
-    x = torch.randn((3100, n_ch), generator=g, device="cuda", dtype=torch.float32)
-    tgt = torch.rand((3100, n_ch), generator=g, device="cuda", dtype=torch.float32) * 3.0
+    n_t = splits[-1][1]
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    tgt = torch.rand((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32) * 3.0
     scale = 1.0 / x.numel()
-    splits = [(0, 1000), (1000, 1001), (1001, 2600), (2600, 3100)]
     st = F.SOSState(sos, n_ch)
     sl = F.StaLtaState(float(nsta), float(nlta), 1.0, n_ch)
     cks = []
@@ -172,9 +171,72 @@ def test_chunked_adjoint_chain_equals_oracle_one_shot(F):
                              scale=scale)
         gx[a:b] = ga
     torch.cuda.synchronize()
+    if raw:
+        return gx.cpu().numpy(), adj.cpu().numpy().T, gs.cpu().numpy(), x.cpu().numpy(), tgt.cpu().numpy(), sos
     _, ogx, ogs, oadj = orc.stalta_grad(sos, x.cpu().numpy().astype(np.float64),
                                         tgt.cpu().numpy().astype(np.float64), nsta, nlta, scale)
-    _check(gx.cpu().numpy(), adj.cpu().numpy().T, gs.cpu().numpy(), ogx, oadj, ogs)
+    return gx.cpu().numpy(), adj.cpu().numpy().T, gs.cpu().numpy(), ogx, oadj, ogs
+
+
+def test_chunked_adjoint_chain_equals_oracle_one_shot(F):
+    _check(*_chain_case(F, 24, 30, 300, [(0, 1000), (1000, 1001), (1001, 2600), (2600, 3100)], 31))
+
+
+# One- to three-sample STA windows with one- and four-sample LTA windows, the
+# STA window both shorter and longer than the LTA window.  A one-sample
+# window has a zero decay: the STA (or LTA) equals the current energy.
+SHORT_WINDOWS = [(1, 1), (1, 4), (2, 1), (2, 4), (3, 1), (3, 4)]
+
+
+def _state_tol(nsta, nlta):
+    """Bar for the adjoint state handed back.  With a one-sample LTA window
+    (and a longer STA window) cf = sta / y^2, and the gradient terms grow like
+    1 / y^5 where y crosses zero; the GPU's block-scan y and the oracle's
+    sequential y differ by FP64 rounding of the order of 1e-13 of the
+    channel's scale, which at the smallest |y| of the data is ~1e-6 of y and
+    is amplified five-fold in the few samples that dominate every gradient.
+    Those cases are held to the gradient bar (1e-5) throughout."""
+    return 1e-5 if nlta == 1 and nsta > 1 else 1e-6
+
+
+# The grad-mode reference passes dL/dcf to the oracle as target = cf - g / 2,
+# which keeps g only to the rounding of cf.  A one-sample LTA window makes cf
+# the ratio of the STA to the current energy, up to ~1e9 near zero crossings
+# of y, where that subtraction loses g (1e-3) entirely; so grad mode runs on
+# the four-sample LTA window only, MSE mode on every pair.
+@pytest.mark.parametrize("nsta,nlta,mode", [(s, l, "mse") for s, l in SHORT_WINDOWS] +
+                         [(s, l, "grad") for s, l in SHORT_WINDOWS if l == 4])
+def test_adjoint_short_windows_one_chunk(F, nsta, nlta, mode):
+    orc = _orc()
+    sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
+    out = _chunk_case(F, 21, 40, 1100, sos, nsta, nlta, 60 + 7 * nsta + nlta, mode)
+    assert all(np.all(np.isfinite(a)) for a in out[:3])
+    _check(*out, tol_state=_state_tol(nsta, nlta))
+
+
+def test_adjoint_equal_one_sample_windows_chunked(F):
+    """nsta = nlta = 1: sta and lta are both the current energy, so cf = 1
+    wherever it is live and the exact gradient is zero; the oracle's and the
+    GPU's values are rounding noise of different arithmetic, so they are not
+    compared with each other.  Bound: the STA/LTA step's two terms at a row
+    are 2 q / y each (they cancel), and the GPU holds them in FP32, so the
+    residue is at most a few FP32 ulps of them; the Butterworth bandpass's
+    gain is at most 1, so each channel's dL/dx stays within 2^-21 of the
+    norm of those terms."""
+    orc = _orc()
+    gx, adj, gs, x, tgt, sos = _chain_case(F, 13, 1, 1, [(0, 3), (3, 700), (700, 701), (701, 2100)], 78, raw=True)
+    assert np.all(np.isfinite(gx)) and np.all(np.isfinite(adj)) and np.all(np.isfinite(gs))
+    y, _ = orc.sos_filter(sos, x.astype(np.float64))
+    q = np.where(np.arange(len(y))[:, None] >= 1, 2.0 * (1.0 - tgt) / x.size, 0.0)
+    terms = np.sqrt(np.sum((2.0 * q / np.where(y != 0, y, np.inf)) ** 2, axis=0))
+    assert np.all(np.linalg.norm(gx, axis=0) <= 2.0 ** -21 * terms)
+
+
+@pytest.mark.parametrize("nsta,nlta", [w for w in SHORT_WINDOWS if w != (1, 1)])
+def test_adjoint_short_windows_chunked(F, nsta, nlta):
+    out = _chain_case(F, 13, nsta, nlta, [(0, 3), (3, 700), (700, 701), (701, 2100)], 70 + 7 * nsta + nlta)
+    assert all(np.all(np.isfinite(a)) for a in out[:3])
+    _check(*out, tol_state=_state_tol(nsta, nlta))
 
 
 def test_autograd_function_matches_oracle(F):

@@ -158,3 +158,27 @@ def test_autotuner_picks_and_caches(F, tmp_path):
     assert gsel in GROUPS
     t2 = Autotuner(path, block=64, waves=4)
     assert t2.group_for(sos, 3000, 1000) == gsel  # from the cache, no measurement
+
+
+def test_tile_change_after_bind_is_refused_until_bound_again(F):
+    """A tile change rebuilds a state's tables, which a bound batch names:
+    the next launch is refused until the batch is bound again, and a bind
+    refuses a state whose block or waves no longer match the batch's."""
+    orc = _orc()
+    sts, soss = _make(F, orc)
+    xs = _inputs(5)
+    ys = [torch.empty_like(x) for x in xs]
+    b = F.Batch(sts)
+    b.bind(xs, ys)
+    b.launch()
+    torch.cuda.synchronize()
+    sts[1].set_tile(64, 4, 8)  # group only: allowed per stream, but the tables are new
+    with pytest.raises(F.FilarkError):
+        b.launch()
+    b.bind(xs, ys)
+    b.launch()
+    torch.cuda.synchronize()
+    sts[2].set_tile(48, 4, 16)  # block differs from the batch's
+    with pytest.raises(F.FilarkError):
+        b.bind(xs, ys)
+    b.close()
