@@ -197,7 +197,7 @@ filark_status filark_state_set(void *st, int kind, const void *host_buf, size_t 
  * waves owns `group` consecutive channels and covers a window of
  * waves * 64 / group blocks of `block` samples per lane; longer chunks run
  * window by window.
- *   kind FILARK_STATE_SOS / _STALTA (forward): block 32, 48 or 64, default 48 x 4 x 8;
+ *   kind FILARK_STATE_SOS / _STALTA (forward): block 32, 48 or 64, default 48 x 8 x 16;
  *   kind FILARK_TILE_SOS_ADJOINT / _STALTA_ADJOINT: block 8 or 16, default 16 x 8 x 8;
  *   waves 1 .. 8;  group 4, 8, 16, 32 or 64.
  * The SOS and STA/LTA states used together must have equal shapes.  _set

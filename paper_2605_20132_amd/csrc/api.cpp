@@ -54,8 +54,8 @@ filark_status fail(filark_status st, const char *fmt, ...) {
 // workgroups fill a CU with 12 waves, three on each SIMD: the VALU-bound
 // passes see no SIMD with more waves than the others.
 constexpr int kDefaultBlock = 48;
-constexpr int kDefaultWaves = 4;
-constexpr int kDefaultGroup = 8;
+constexpr int kDefaultWaves = 8;
+constexpr int kDefaultGroup = 16;
 
 struct Tile {
   int block = kDefaultBlock;  // L: samples per lane block
@@ -358,6 +358,8 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
   p.n_grp = (int)((n_ch + t.group - 1) / t.group);
   p.per_xcd = per_xcd_for(p.n_grp);
   p.n_lev = t.levels();
+  p.nt = t.group >= 16 ? 1 : 0;
+  p.order = t.group >= 16 ? 1 : 0;
   if (sos) {
     p.zs = zs;
     p.coef = sos->fwd.d;

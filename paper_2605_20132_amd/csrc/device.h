@@ -51,9 +51,32 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, int ran
 __device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
 }
+// NT: the non-temporal hint, for outputs never read again.  It pays where a
+// workgroup writes at least 64 contiguous bytes of a row (the lines go out
+// without lingering in L2); with 32-byte row pieces the partial lines of
+// neighbouring workgroups no longer merge in L2 and every piece becomes its
+// own memory write, so narrow groups store without it.
+template <bool NT = false>
 __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t voff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, 0, NT ? 2 : 0);
 }
+
+// Row j of a lane's block through a buffer resource rebased to that row:
+// base + j * rb with the range shortened by as much (never below zero), so
+// the lane keeps its block-start offset for every row (no per-row vector
+// address arithmetic; the rebasing is scalar) and the range check still
+// drops exactly the rows past the end.  range and j * rb stay below 2^31.
+struct RowBuf {
+  const char *base;
+  uint32_t range, rb;
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t at(int j) const {
+    const uint32_t d = (uint32_t)j * rb;
+    int r = (int)range - (int)d;
+    r = r < 0 ? 0 : r;
+    asm volatile("" : "+s"(r));  // scalar: a vector select here would make every access a loop over lanes
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(base + d), (short)0, r, 0x00020000);
+  }
+};
 
 // Workgroup barrier for data exchanged through LDS only: each wave waits for
 // its own LDS operations, then all waves meet.  Unlike __syncthreads() it
@@ -193,9 +216,22 @@ __device__ __forceinline__ void project(cdouble *G, const float (&xv)[L], double
 // round-robin by index, so workgroup w runs on XCD w % 8; XCD x is given the
 // contiguous slab of groups [x * per_xcd, (x + 1) * per_xcd), which keeps the
 // rows of neighbouring groups, which share cache lines, in one L2.
-__device__ __forceinline__ int group_of(int per_xcd) {
+//   order 0: the XCD's workgroups take the slab in dispatch order, so the
+//            groups that share a line run side by side (their partial-line
+//            writes merge in L2: needed by 32-byte row pieces);
+//   order 1: dispatch position p takes the p-th of 0, 3, 6, ..., 1, 4, 7, ...,
+//            2, 5, 8, ...: the workgroups each CU receives first then cover
+//            every line of every row together, which measured faster for
+//            groups writing 64-byte pieces with the non-temporal hint.
+__device__ __forceinline__ int group_of(int per_xcd, int order = 0) {
   const int wg = (int)blockIdx.x;
-  return uniform((wg & 7) * per_xcd + (wg >> 3));
+  const int p = wg >> 3;
+  int q = p;
+  if (order == 1) {
+    const int c0 = (per_xcd + 2) / 3, c1 = (per_xcd + 1) / 3;  // counts of 0 and 1 mod 3 below per_xcd
+    q = p < c0 ? 3 * p : (p < c0 + c1 ? 3 * (p - c0) + 1 : 3 * (p - c0 - c1) + 2);
+  }
+  return uniform((wg & 7) * per_xcd + q);
 }
 
 }  // namespace dev

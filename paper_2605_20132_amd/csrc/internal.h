@@ -30,6 +30,8 @@ struct FwdParams {
   int32_t n_lev;       // scan levels (>= 1; level k spans 2^k blocks)
   int32_t range;       // bytes of one [n_t][n_ch] FP32 array (buffer range)
   int32_t out_range;   // buffer range of y and cf: `range`, or 0 to write neither (states only)
+  int32_t nt;          // 1: y and cf stores carry the non-temporal hint (groups of >= 16 channels)
+  int32_t order;       // channel-group order within an XCD (dev::group_of)
 
   // SOS cascade
   double *zs;          // carried state [2K][n_ch], updated in place
@@ -125,6 +127,14 @@ struct BatchParams {
 
 // Dynamic LDS bytes of a forward workgroup.
 size_t fwd_lds_bytes(int K, int nw, int n_lev, int cw);
+
+// Launchers of one block length (fwd_l32.hip, fwd_l48.hip, fwd_l64.hip).
+hipError_t launch_fwd_l32(const FwdParams &p, int K, bool stalta, bool write_y, bool unit, bool rev,
+                          hipStream_t stream);
+hipError_t launch_fwd_l48(const FwdParams &p, int K, bool stalta, bool write_y, bool unit, bool rev,
+                          hipStream_t stream);
+hipError_t launch_fwd_l64(const FwdParams &p, int K, bool stalta, bool write_y, bool unit, bool rev,
+                          hipStream_t stream);
 
 // Host-side launcher (defined in fwd.hip).  K = 0 means STA/LTA only.
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, bool rev,
