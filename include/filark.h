@@ -147,11 +147,25 @@ filark_status filark_stalta_init(filark_stalta_t *st, double sta_s, double lta_s
  * response is |H|^2 and the phase is zero; no edge padding is added.  Uses
  * the coefficients and tile of `st` (which must have 48-sample blocks, the
  * default); its carried state is neither read nor changed.  in / out: device FP32 [n_t][n_ch] (in == out allowed); n_ch must
- * equal the state's and be below 2^23.  Asynchronous on `stream` (not for
- * graph capture: it clears its work state with hipMemsetAsync).
+ * equal the state's and be below 2^23.  Asynchronous on `stream`.  The
+ * passes' own filter state [2K][n_ch] FP64 is a workspace of `st`, allocated
+ * on the first call (and grown on a larger one), then cleared by a kernel.
  */
 filark_status filark_sos_filtfilt(filark_sos_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
                                   hipStream_t stream);
+
+/*
+ * filark_sos_filtfilt without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and kernels;
+ * the passes' filter state lives in a fixed 1 MiB array that each GPU holds
+ * for the life of the process, so 2 * n_sec * n_ch must not exceed 131072
+ * (FILARK_EINVAL otherwise, before anything is enqueued).  Every call on one
+ * GPU uses the same array: calls that overlap on a GPU (other streams, other
+ * threads) race.
+ */
+filark_status filark_sos_filtfilt_noalloc(filark_sos_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                                          hipStream_t stream);
 
 /*
  * STA/LTA of one chunk of an already filtered signal.

@@ -35,7 +35,7 @@ EXPORTS = (
     "filark_state_load", "filark_sos_stalta_adjoint", "filark_batch_create", "filark_batch_bind",
     "filark_batch_launch", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
     "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
-    "filark_sos_filtfilt", "filark_ema_init", "filark_ema_process", "filark_ema_state_get", "filark_ema_state_set",
+    "filark_sos_filtfilt", "filark_sos_filtfilt_noalloc", "filark_ema_init", "filark_ema_process", "filark_ema_state_get", "filark_ema_state_set",
     "filark_ema_destroy", "filark_fir_init", "filark_fir_set_tile", "filark_fir_process", "filark_fir_state_get",
     "filark_fir_state_set", "filark_fir_destroy",
 )
@@ -65,6 +65,7 @@ def lib():
     L.filark_sos_init.argtypes = [ctypes.POINTER(vp), D, ctypes.c_int, i64, ctypes.c_uint, vp]
     L.filark_sos_process.argtypes = [vp, vp, vp, i64, i64, vp]
     L.filark_sos_filtfilt.argtypes = [vp, vp, vp, i64, i64, vp]
+    L.filark_sos_filtfilt_noalloc.argtypes = [vp, vp, vp, i64, i64, vp]
     L.filark_stalta_init.argtypes = [ctypes.POINTER(vp), ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      i64, vp]
     L.filark_stalta_process.argtypes = [vp, vp, vp, i64, i64, vp]
@@ -185,6 +186,14 @@ class SOSState:
             out = torch.empty_like(x)
         _check(lib().filark_sos_filtfilt(self._h, _dev_f32(x, "x"), _dev_f32(out, "out"), x.shape[1],
                                          x.shape[0], _stream(stream)))
+        return out
+
+    def filtfilt_noalloc(self, x, out, stream=None):
+        """filtfilt() through the allocation-free entry point: the passes'
+        state lives in a fixed per-GPU array (2 * sections * channels <=
+        131072); `out` must be given.  Overlapping calls on one GPU race."""
+        _check(lib().filark_sos_filtfilt_noalloc(self._h, _dev_f32(x, "x"), _dev_f32(out, "out"), x.shape[1],
+                                                 x.shape[0], _stream(stream)))
         return out
 
     def get_state(self, stream=None) -> np.ndarray:

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -465,6 +466,78 @@ filark_status check_tile(int block, int waves, int group, bool adjoint) {
   return FILARK_OK;
 }
 
+// Scratch of the allocation-free zero-phase entry point: the two passes' own
+// FP64 filter state [2K][n_ch], at most 1 MiB (2 * sections * channels <=
+// 131072).  Each GPU the library runs on holds its own copy until the
+// process ends; every call on one GPU shares it, so calls that overlap on a
+// GPU race.  In host code `scratch` is only a stand-in for the symbol: the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current, and is the only form passed to
+// kernels.
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) double scratch[131072];
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// The device address of `dev`'s scratch (dev must be current).
+filark_status scratch_on(int dev, double **out) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(FILARK_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FILARK_EHIP, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double *>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return FILARK_OK;
+}
+
+// Zero n doubles (a fill kernel rather than hipMemsetAsync, so a captured
+// graph replays it correctly).
+__global__ void __launch_bounds__(256) fill_zero_kernel(double *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+hipError_t fill_zero(double *p, size_t n, hipStream_t stream) {
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(blocks), dim3(256), 0, stream, p, n);
+  return hipGetLastError();
+}
+
+filark_status filtfilt_check(const filark_sos_state *sos, const float *in, const float *out, int64_t n_ch,
+                             int64_t n_t) {
+  if (!sos) return fail(FILARK_EINVAL, "null state");
+  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
+  if (n_ch != sos->n_ch)
+    return fail(FILARK_ESHAPE, "n_ch %lld differs from the SOS state's %lld", (long long)n_ch, (long long)sos->n_ch);
+  if (n_t == 0) return FILARK_OK;
+  if (!in || !out) return fail(FILARK_EINVAL, "null input or output pointer");
+  const Tile &t = sos->fwd.tile;
+  if (t.block != 48) return fail(FILARK_EINVAL, "zero-phase filtering runs on 48-sample blocks (the default tile)");
+  if (launch_rows(t, n_ch) == 0) return fail(FILARK_EINVAL, "n_ch %lld too large for the tile", (long long)n_ch);
+  const int K = sos->cas.K;
+  return check_lds(fwd_lds_bytes(K, t.waves, t.levels(), t.group), t, K, sos->device);
+}
+
+// Forward pass from rest, then the time-reversed pass over its output from
+// rest (in place), with `work` [2K][n_ch] as the passes' filter state; the
+// object's carried state is not touched.
+hipError_t filtfilt_launches(const filark_sos_state *sos, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                             double *work, hipStream_t stream) {
+  const Tile &t = sos->fwd.tile;
+  const size_t n = (size_t)(2 * sos->cas.K) * (size_t)n_ch;
+  hipError_t e = fill_zero(work, n, stream);
+  if (e == hipSuccess)
+    e = forward_launches(sos, nullptr, t, work, nullptr, nullptr, in, out, nullptr, false, n_ch, n_t, stream);
+  if (e == hipSuccess) e = fill_zero(work, n, stream);
+  if (e == hipSuccess)
+    e = forward_launches(sos, nullptr, t, work, nullptr, nullptr, out, out, nullptr, false, n_ch, n_t, stream, true);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -568,34 +641,35 @@ filark_status filark_sos_process(filark_sos_t st, const float *in, float *out, i
 
 filark_status filark_sos_filtfilt(filark_sos_t sos, const float *in, float *out, int64_t n_ch, int64_t n_t,
                                   hipStream_t stream) {
-  if (!sos) return fail(FILARK_EINVAL, "null state");
-  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
-  if (n_ch != sos->n_ch)
-    return fail(FILARK_ESHAPE, "n_ch %lld differs from the SOS state's %lld", (long long)n_ch, (long long)sos->n_ch);
-  if (n_t == 0) return FILARK_OK;
-  if (!in || !out) return fail(FILARK_EINVAL, "null input or output pointer");
-  const Tile &t = sos->fwd.tile;
-  if (t.block != 48) return fail(FILARK_EINVAL, "zero-phase filtering runs on 48-sample blocks (the default tile)");
-  if (launch_rows(t, n_ch) == 0) return fail(FILARK_EINVAL, "n_ch %lld too large for the tile", (long long)n_ch);
-  const int K = sos->cas.K;
-  filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels(), t.group), t, K, sos->device);
-  if (rc != FILARK_OK) return rc;
+  filark_status rc = filtfilt_check(sos, in, out, n_ch, n_t);
+  if (rc != FILARK_OK || n_t == 0) return rc;
   const int prev_dev = current_device();
   if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
-  const size_t bytes = (size_t)(2 * K) * (size_t)n_ch * sizeof(double);
+  const size_t bytes = (size_t)(2 * sos->cas.K) * (size_t)n_ch * sizeof(double);
   rc = grow(&sos->d_ff, &sos->ff_bytes, bytes, stream);
   hipError_t e = hipSuccess;
-  if (rc == FILARK_OK) {
-    // forward pass from rest, then the time-reversed pass over its output
-    // from rest (in place); the object's carried state is not touched
-    e = hipMemsetAsync(sos->d_ff, 0, bytes, stream);
-    if (e == hipSuccess)
-      e = forward_launches(sos, nullptr, t, sos->d_ff, nullptr, nullptr, in, out, nullptr, false, n_ch, n_t, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(sos->d_ff, 0, bytes, stream);
-    if (e == hipSuccess)
-      e = forward_launches(sos, nullptr, t, sos->d_ff, nullptr, nullptr, out, out, nullptr, false, n_ch, n_t, stream,
-                           true);
-  }
+  if (rc == FILARK_OK) e = filtfilt_launches(sos, in, out, n_ch, n_t, sos->d_ff, stream);
+  if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
+  if (rc != FILARK_OK) return rc;
+  if (e != hipSuccess) return fail(FILARK_EHIP, "zero-phase launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status filark_sos_filtfilt_noalloc(filark_sos_t sos, const float *in, float *out, int64_t n_ch, int64_t n_t,
+                                          hipStream_t stream) {
+  filark_status rc = filtfilt_check(sos, in, out, n_ch, n_t);
+  if (rc != FILARK_OK || n_t == 0) return rc;
+  const size_t bytes = (size_t)(2 * sos->cas.K) * (size_t)n_ch * sizeof(double);
+  if (bytes > sizeof(scratch))
+    return fail(FILARK_EINVAL, "the work state of %d sections x %lld channels needs %zu bytes; the allocation-free "
+                "entry point holds at most %zu (2 * sections * channels <= %zu)", sos->cas.K, (long long)n_ch,
+                bytes, sizeof(scratch), sizeof(scratch) / sizeof(double));
+  const int prev_dev = current_device();
+  if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
+  double *work = nullptr;
+  rc = scratch_on(sos->device, &work);
+  hipError_t e = hipSuccess;
+  if (rc == FILARK_OK) e = filtfilt_launches(sos, in, out, n_ch, n_t, work, stream);
   if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
   if (rc != FILARK_OK) return rc;
   if (e != hipSuccess) return fail(FILARK_EHIP, "zero-phase launch failed: %s", hipGetErrorString(e));
