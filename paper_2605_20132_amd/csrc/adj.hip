@@ -107,9 +107,44 @@ struct SlBack {
   }
 };
 
+// Sum of the coefficient gradients over the lanes of a wave by recursive
+// halving: at each of five exchange steps a lane gives away half of its
+// (zero-padded) 32 values and adds the half its partner gives away, so a
+// lane ends with one value, index lane >> 1, summed over its 32-lane half,
+// and a last exchange completes the sum over all 64 lanes: 32 exchanged
+// values per lane instead of 6 per coefficient.  Fixed order, so the result
+// does not depend on timing.  Returns the sum of value (lane >> 1).
+template <int NC>
+__device__ __forceinline__ double wave_sum_halving(const double (&gc)[NC]) {
+  static_assert(NC <= 32, "at most 32 values");
+  const int lane = threadIdx.x & (kWave - 1);
+  double v[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) v[i] = i < NC ? gc[i] : 0.0;
+#pragma unroll
+  for (int n = 32, m = 32; n > 1; n >>= 1, m >>= 1) {
+    const bool hi = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < n / 2; ++i) {
+      const double give = hi ? v[i] : v[i + n / 2];
+      const double keep = hi ? v[i + n / 2] : v[i];
+      v[i] = keep + shfl_xor_d(give, m);
+    }
+  }
+  return v[0] + shfl_xor_d(v[0], 1);
+}
+
 // UNIT: every section after the first has b0 = b2 = 1 (Butterworth designs),
 // so those sections skip the multiplications by them (bit-identical results).
-template <int K, int L, bool UNIT>
+// RECON: the section inputs and outputs of each row, which the coefficient
+// gradients need in reverse time, are rebuilt backwards from the forward
+// state after the block's last row and the input x (each section's state
+// update inverted: y = (z2' - b2 v) / (-a2), or (z1' - b1 v) / (-a1) for a
+// first-order section), in FP64, instead of being stored per row during the
+// forward recompute; the host selects it when every section is invertible
+// with |a2| >= 1/4 (first order: |a1| >= 1/2, b2 = 0), which bounds the
+// growth of rounding over a 16-row block by 2^16.
+template <int K, int L, bool UNIT, bool RECON>
 __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
   constexpr int NS = 2 * K, NSP = NS + 1, NC = 5 * K;
   constexpr bool kSgprLevels = K <= 4;
@@ -164,7 +199,9 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
   lds_barrier();  // level matrices and the checkpointed state are in LDS
 
   // ---------------- forward recompute: filter ----------------
-  float yk[K][L];                 // output of section k at each row of the block
+  float yk[RECON ? 1 : K][L];     // output of section k at each row of the block (stored variant)
+  float yo[RECON ? L : 1];        // the cascade output at each row (rebuilding variant)
+  double zend[RECON ? NS : 1];    // forward state after the block's last row (rebuilding variant)
   double s_loc = 0.0, l_loc = 0.0;  // STA/LTA sums from zero over the block's valid rows
   {
     double a[NS];
@@ -218,11 +255,16 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
         const double yy = unit ? v + z[2 * k] : fma(coef[5 * k + 0], v, z[2 * k]);
         z[2 * k] = fma(coef[5 * k + 3], yy, fma(coef[5 * k + 1], v, z[2 * k + 1]));
         z[2 * k + 1] = fma(coef[5 * k + 4], yy, unit ? v : coef[5 * k + 2] * v);
-        yk[k][j] = (float)yy;
+        if constexpr (!RECON) yk[k][j] = (float)yy;
         v = yy;
       }
+      if constexpr (RECON) yo[j] = (float)v;
       // sums from the rounded output, the value the backward pass sees
-      const double yd = widen<2>(yk[K - 1][j]);
+      double yd;
+      if constexpr (RECON)
+        yd = widen<2>(yo[j]);
+      else
+        yd = widen<2>(yk[K - 1][j]);
       const double e = yd * yd;
       if (j < nv) {
         s_loc = fma(asd, s_loc, e);
@@ -230,7 +272,19 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       }
       __builtin_amdgcn_sched_barrier(0);
     }
+    if constexpr (RECON) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) zend[i] = z[i];
+    }
   }
+
+  // the cascade output of row j, as the STA/LTA sees it
+  auto yout = [&](int j) -> float {
+    if constexpr (RECON)
+      return yo[j];
+    else
+      return yk[K - 1][j];
+  };
 
   // ---------------- forward recompute: STA/LTA sums at block starts ----------------
   int64_t g0 = 0;
@@ -284,7 +338,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
 #pragma unroll
     for (int j = 0; j < L; ++j) {
       float al = 0.0f, be = 0.0f;
-      if (j < nv) sf.step(S, Lg, widen<3>(yk[K - 1][j]), widen<4>(gv[j]), g0 + row0 + j, al, be);
+      if (j < nv) sf.step(S, Lg, widen<3>(yout(j)), widen<4>(gv[j]), g0 + row0 + j, al, be);
       gv[j] = al;
       bt[j] = be;
       __builtin_amdgcn_sched_barrier(0);
@@ -304,7 +358,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     // from the block end to its start, from zero (or the handed-in state)
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
-      if (j < nv) (void)sb.step(A, B, widen<5>(yk[K - 1][j]), gv[j], bt[j]);
+      if (j < nv) (void)sb.step(A, B, widen<5>(yout(j)), gv[j], bt[j]);
       __builtin_amdgcn_sched_barrier(0);
     }
     cdouble *dp = as_const(q->dpow);
@@ -336,7 +390,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
       float v = 0.0f;
-      if (j < nv) v = (float)sb.step(Ax, Bx, widen<6>(yk[K - 1][j]), gv[j], bt[j]);
+      if (j < nv) v = (float)sb.step(Ax, Bx, widen<6>(yout(j)), gv[j], bt[j]);
       yb[j] = v;
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -411,14 +465,54 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     for (int i = 0; i < NC; ++i) gc[i] = 0.0;
     const __amdgpu_buffer_rsrc_t rgx = rsrc(q->gx, q->range);
     const uint32_t rb = fresh(rowb);
+    double zr[RECON ? NS : 1];  // rebuilding variant: forward state after the current row
+    if constexpr (RECON) {
+#pragma unroll
+      for (int i = 0; i < NS; ++i) zr[i] = zend[i];
+    }
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
       double ybar = widen<7>(yb[j]);
+      // section inputs and outputs of the row
+      double vk[K], yk_d[K];
+      if constexpr (RECON) {
+        // invert the forward step of each section, first to last: from the
+        // state after the row and the section's input, its output and the
+        // state before the row (rows past the end, x = 0, are undone too)
+        double v = widen<8>(xv[j]);
+        aparams_t qr = aparams();
+        cdouble *ri = as_const(qr->rinv);
+        const int first_order = qr->first_order;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double z1a = zr[2 * k], z2a = zr[2 * k + 1];
+          const bool unit = UNIT && k > 0;
+          double y;
+          if ((first_order >> k) & 1) {  // a2 = b2 = 0: z1' = b1 v - a1 y, z2 = 0
+            y = fma(-coef[5 * k + 1], v, z1a) * ri[k];
+            zr[2 * k] = unit ? y - v : fma(-coef[5 * k + 0], v, y);
+            zr[2 * k + 1] = 0.0;
+          } else {  // z2' = b2 v - a2 y
+            y = (unit ? z2a - v : fma(-coef[5 * k + 2], v, z2a)) * ri[k];
+            zr[2 * k] = unit ? y - v : fma(-coef[5 * k + 0], v, y);
+            zr[2 * k + 1] = fma(-coef[5 * k + 3], y, fma(-coef[5 * k + 1], v, z1a));
+          }
+          vk[k] = v;
+          yk_d[k] = y;
+          v = y;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          vk[k] = k == 0 ? widen<8>(xv[j]) : widen<9>(yk[k - 1][j]);
+          yk_d[k] = widen<9>(yk[k][j]);
+        }
+      }
       if (j < nv) {
 #pragma unroll
         for (int k = K - 1; k >= 0; --k) {
-          const double vin = k == 0 ? widen<8>(xv[j]) : widen<9>(yk[k - 1][j]);
-          const double yout = widen<9>(yk[k][j]);
+          const double vin = vk[k];
+          const double yout = yk_d[k];
           const double u1 = u[2 * k], u2 = u[2 * k + 1];
           const double ys = fma(coef[5 * k + 4], u2, fma(coef[5 * k + 3], u1, ybar));
           gc[5 * k + 0] = fma(ys, vin, gc[5 * k + 0]);
@@ -443,13 +537,19 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       adj[(NS + 1) * n_ch + c] = xsl[2 * my + 1];
     }
 
-    // coefficient gradients: wave butterfly, then the waves in order
+    // coefficient gradients: over the wave (recursive halving up to 32
+    // values, else a butterfly per value), then the waves in order
+    if constexpr (NC <= 32) {
+      const double v = wave_sum_halving<NC>(gc);
+      if ((lane & 1) == 0 && (lane >> 1) < NC) wsum[w * NC + (lane >> 1)] = v;
+    } else {
 #pragma unroll
-    for (int i = 0; i < NC; ++i) {
-      double v = gc[i];
+      for (int i = 0; i < NC; ++i) {
+        double v = gc[i];
 #pragma unroll
-      for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
-      if (lane == 0) wsum[w * NC + i] = v;
+        for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_d(v, m);
+        if (lane == 0) wsum[w * NC + i] = v;
+      }
     }
     lds_barrier();
     if (threadIdx.x < NC) {
@@ -461,10 +561,10 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
   }
 }
 
-template <int K, int L, bool U>
+template <int K, int L, bool U, bool RC>
 hipError_t launch_u(const AdjParams &p, hipStream_t stream) {
   const size_t lds = adj_lds_bytes(K, p.nw, p.n_lev);
-  hipLaunchKernelGGL((adj_kernel<K, L, U>), dim3((unsigned)grid_for(p.per_xcd)),
+  hipLaunchKernelGGL((adj_kernel<K, L, U, RC>), dim3((unsigned)grid_for(p.per_xcd)),
                      dim3((unsigned)(p.nw * kWave)), lds, stream, p);
   return hipGetLastError();
 }
@@ -472,9 +572,9 @@ hipError_t launch_u(const AdjParams &p, hipStream_t stream) {
 template <int K, int L>
 hipError_t launch_one(const AdjParams &p, bool unit, hipStream_t stream) {
   if constexpr (K >= 2 && L == 16) {  // the default adjoint block only
-    if (unit) return launch_u<K, L, true>(p, stream);
+    if (unit) return p.recon ? launch_u<K, L, true, true>(p, stream) : launch_u<K, L, true, false>(p, stream);
   }
-  return launch_u<K, L, false>(p, stream);
+  return p.recon ? launch_u<K, L, false, true>(p, stream) : launch_u<K, L, false, false>(p, stream);
 }
 
 template <int L>

@@ -113,6 +113,27 @@ struct Cascade {
       if (c[k][0] != 1.0 || c[k][2] != 1.0) return false;
     return true;
   }
+  // bit k: section k is first order (a2 = b2 = 0)
+  int first_order_bits() const {
+    int m = 0;
+    for (int k = 0; k < K; ++k)
+      if (c[k][4] == 0.0 && c[k][2] == 0.0) m |= 1 << k;
+    return m;
+  }
+  // the adjoint may rebuild section signals backwards: every section's state
+  // update is invertible with |a2| >= 1/4 (first order: |a1| >= 1/2), so
+  // undoing 16 rows grows rounding by at most 2^16
+  bool invertible() const {
+    for (int k = 0; k < K; ++k) {
+      const double b2 = c[k][2], a1 = c[k][3], a2 = c[k][4];
+      if (a2 != 0.0) {
+        if (!(std::fabs(a2) >= 0.25)) return false;
+      } else if (b2 != 0.0 || !(std::fabs(a1) >= 0.5)) {
+        return false;
+      }
+    }
+    return true;
+  }
 };
 
 // One direct-form-II-transposed step of the whole cascade.
@@ -166,7 +187,7 @@ int current_device() {
 struct Tables {
   Tile tile;
   double *d = nullptr;
-  size_t off_G = 0, off_P = 0;
+  size_t off_G = 0, off_P = 0, off_R = 0;
 };
 
 struct filark_sos_state {
@@ -176,6 +197,7 @@ struct filark_sos_state {
   double *d_state = nullptr;  // [2K][n_ch]
   Tables fwd;                 // forward kernel
   Tables adj;                 // adjoint kernel
+  Tables ckp;                 // forward pass that checkpoints the adjoint's window starts
   uint64_t gen = 0;           // bumped whenever the forward tables are rebuilt
   // adjoint workspace: window checkpoints and per-group coefficient sums
   double *d_ck = nullptr;
@@ -194,6 +216,7 @@ struct filark_stalta_state {
   int64_t *d_cnt = nullptr;   // [n_ch] global sample counter
   Tables fwd;
   Tables adj;
+  Tables ckp;
 };
 
 struct filark_batch {
@@ -254,15 +277,34 @@ namespace {
 // row segments per group; the kernels are compiled for 48-row blocks only).
 constexpr int kTrigBlock = 48, kTrigWaves = 8, kTrigGroup = 16;
 
-// Default adjoint tile: 16-sample blocks, 8 waves, groups of 8 channels
-// (windows of 1024 rows).
+// Default adjoint tile: 16-sample blocks, 4 waves, groups of 8 channels
+// (windows of 512 rows; three workgroups per CU when the section signals are
+// rebuilt rather than stored).
 Tile default_adj_tile() {
   Tile t;
   t.block = 16;
-  t.waves = 8;
+  t.waves = 4;
   t.group = 8;
   return t;
 }
+
+// Tile of the forward pass that writes the adjoint's window checkpoints:
+// 64-row blocks, so any adjoint window that is a multiple of 64 rows and
+// divides the 2048-row window starts on a block.
+Tile checkpoint_tile() {
+  Tile t;
+  t.block = 64;
+  t.waves = 4;
+  t.group = 8;
+  return t;
+}
+
+// Checkpoint emission of a forward launch (FwdParams::ck).
+struct CkSpec {
+  double *base;     // slot of the first checkpoint after the launch start
+  int64_t stride;   // doubles per slot
+  int rows;         // rows between checkpoints (a multiple of the block)
+};
 
 filark_status upload(double **dst, const std::vector<double> &tab, hipStream_t stream) {
   if (*dst) {
@@ -299,6 +341,13 @@ filark_status sos_tables(const Cascade &cas, Tables &tb, hipStream_t stream) {
   for (int k = 0; k < tb.tile.levels(); ++k) {
     tab.insert(tab.end(), P.begin(), P.end());
     P = matmul(P, P, n);
+  }
+  // reciprocals that invert each section's state update (adjoint kernel):
+  // 1 / (-a2), or 1 / (-a1) for a first-order section, 0 where undefined
+  tb.off_R = tab.size();
+  for (int k = 0; k < K; ++k) {
+    const double a1 = cas.c[k][3], a2 = cas.c[k][4];
+    tab.push_back(a2 != 0.0 ? -1.0 / a2 : (a1 != 0.0 ? -1.0 / a1 : 0.0));
   }
   return upload(&tb.d, tab, stream);
 }
@@ -347,7 +396,7 @@ int64_t launch_rows(const Tile &t, int64_t n_ch) {
 hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_state *sl, const Tile &t,
                             double *zs, double *slst, int64_t *cnt, const float *in, float *y, float *cf,
                             bool states_only, int64_t n_ch, int64_t n_t, hipStream_t stream,
-                            bool rev = false) {
+                            bool rev = false, const CkSpec *ck = nullptr, bool ckp_tables = false) {
   const uint64_t rowb = (uint64_t)n_ch * 4u;
   const int64_t rows = launch_rows(t, n_ch);
   const int K = sos ? sos->cas.K : 0;
@@ -362,15 +411,16 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
   p.nt = t.group >= 16 ? 1 : 0;
   p.order = t.group >= 16 ? 1 : 0;
   if (sos) {
+    const Tables &tb = ckp_tables ? sos->ckp : sos->fwd;
     p.zs = zs;
-    p.coef = sos->fwd.d;
-    p.G = sos->fwd.d + sos->fwd.off_G;
-    p.Pw = sos->fwd.d + sos->fwd.off_P;
+    p.coef = tb.d;
+    p.G = tb.d + tb.off_G;
+    p.Pw = tb.d + tb.off_P;
   }
   if (sl) {
     p.sl = slst;
     p.cnt = cnt;
-    p.dpow = sl->fwd.d;
+    p.dpow = (ckp_tables ? sl->ckp : sl->fwd).d;
     p.nlta = sl->nlta;
     p.nsta_d = (double)sl->nsta;
     p.nlta_d = (double)sl->nlta;
@@ -393,6 +443,11 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
     p.n_t = (int32_t)nt;
     p.range = (int32_t)((uint64_t)nt * rowb);
     p.out_range = states_only ? 0 : p.range;
+    if (ck) {
+      p.ck = ck->base + (t0 / ck->rows) * ck->stride;
+      p.ck_stride = ck->stride;
+      p.ck_blocks = ck->rows / t.block;
+    }
     e = launch_fwd(p, K, t.block, sl != nullptr, !states_only && (sl == nullptr || y != nullptr),
                    sos != nullptr && sos->cas.unit_tail(), rev, stream);
   }
@@ -588,8 +643,10 @@ filark_status filark_sos_init(filark_sos_t *out, const double *sos, int n_sec, i
   if (e == hipSuccess) e = hipMemsetAsync(st->d_state, 0, bytes, stream);
   if (e != hipSuccess) rc = fail(FILARK_EHIP, "state allocation: %s", hipGetErrorString(e));
   st->adj.tile = default_adj_tile();
+  st->ckp.tile = checkpoint_tile();
   if (rc == FILARK_OK) rc = sos_tables(st->cas, st->fwd, stream);
   if (rc == FILARK_OK) rc = sos_tables(st->cas, st->adj, stream);
+  if (rc == FILARK_OK) rc = sos_tables(st->cas, st->ckp, stream);
   if (rc != FILARK_OK) {
     filark_sos_destroy(st);
     return rc;
@@ -615,16 +672,19 @@ filark_status filark_stalta_init(filark_stalta_t *out, double sta_s, double lta_
   st->n_ch = n_ch;
   st->nsta = (int64_t)ns;
   st->nlta = (int64_t)nl;
-  const size_t bytes = 2 * (size_t)n_ch * sizeof(double);
+  // (sta, lta) [2][n_ch] and the counter [n_ch] in one allocation, so a
+  // device checkpoint of the whole state is one copy
+  const size_t bytes = (size_t)n_ch * (2 * sizeof(double) + sizeof(int64_t));
   filark_status rc = FILARK_OK;
   hipError_t e = hipMalloc(&st->d_state, bytes);
   if (e == hipSuccess) e = hipMemsetAsync(st->d_state, 0, bytes, stream);
-  if (e == hipSuccess) e = hipMalloc(&st->d_cnt, (size_t)n_ch * sizeof(int64_t));
-  if (e == hipSuccess) e = hipMemsetAsync(st->d_cnt, 0, (size_t)n_ch * sizeof(int64_t), stream);
+  if (e == hipSuccess) st->d_cnt = reinterpret_cast<int64_t *>(st->d_state + 2 * (size_t)n_ch);
   if (e != hipSuccess) rc = fail(FILARK_EHIP, "state allocation: %s", hipGetErrorString(e));
   st->adj.tile = default_adj_tile();
+  st->ckp.tile = checkpoint_tile();
   if (rc == FILARK_OK) rc = stalta_tables(st->nsta, st->nlta, st->fwd, stream);
   if (rc == FILARK_OK) rc = stalta_tables(st->nsta, st->nlta, st->adj, stream);
+  if (rc == FILARK_OK) rc = stalta_tables(st->nsta, st->nlta, st->ckp, stream);
   if (rc != FILARK_OK) {
     filark_stalta_destroy(st);
     return rc;
@@ -836,11 +896,8 @@ filark_status filark_state_save(const void *obj, int kind, void *dev_dst, hipStr
   }
   if (kind == FILARK_STATE_STALTA) {
     const filark_stalta_state *st = static_cast<const filark_stalta_state *>(obj);
-    char *d = static_cast<char *>(dev_dst);
-    const size_t b1 = 2 * (size_t)st->n_ch * sizeof(double);
-    HIP_TRY(hipMemcpyAsync(d, st->d_state, b1, hipMemcpyDeviceToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(d + b1, st->d_cnt, (size_t)st->n_ch * sizeof(int64_t), hipMemcpyDeviceToDevice,
-                           stream));
+    HIP_TRY(hipMemcpyAsync(dev_dst, st->d_state, (size_t)st->n_ch * (2 * sizeof(double) + sizeof(int64_t)),
+                           hipMemcpyDeviceToDevice, stream));
     return FILARK_OK;
   }
   return fail(FILARK_EINVAL, "unknown state kind %d", kind);
@@ -856,11 +913,8 @@ filark_status filark_state_load(void *obj, int kind, const void *dev_src, hipStr
   }
   if (kind == FILARK_STATE_STALTA) {
     filark_stalta_state *st = static_cast<filark_stalta_state *>(obj);
-    const char *d = static_cast<const char *>(dev_src);
-    const size_t b1 = 2 * (size_t)st->n_ch * sizeof(double);
-    HIP_TRY(hipMemcpyAsync(st->d_state, d, b1, hipMemcpyDeviceToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(st->d_cnt, d + b1, (size_t)st->n_ch * sizeof(int64_t), hipMemcpyDeviceToDevice,
-                           stream));
+    HIP_TRY(hipMemcpyAsync(st->d_state, dev_src, (size_t)st->n_ch * (2 * sizeof(double) + sizeof(int64_t)),
+                           hipMemcpyDeviceToDevice, stream));
     return FILARK_OK;
   }
   return fail(FILARK_EINVAL, "unknown state kind %d", kind);
@@ -891,8 +945,8 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
   const int prev_dev = current_device();
   if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
 
-  // workspace: forward state at every window start (filter [2K][n_ch],
-  // STA/LTA [2][n_ch], counter [n_ch]), per-group coefficient sums
+  // workspace: forward state at every window start after the first (filter
+  // [2K][n_ch], STA/LTA [2][n_ch], counter [n_ch]), per-group coefficient sums
   const int64_t n_win = (n_t + rows - 1) / rows;
   const size_t ck_doubles = (size_t)(2 * K + 3) * (size_t)n_ch;  // the counter rides in a double slot
   const int n_grp = (int)((n_ch + ta.group - 1) / ta.group);
@@ -905,18 +959,49 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
   auto ck_z = [&](int64_t w) { return sos->d_ck + (size_t)w * ck_doubles; };
   auto ck_s = [&](int64_t w) { return ck_z(w) + (size_t)(2 * K) * n_ch; };
   auto ck_c = [&](int64_t w) { return reinterpret_cast<int64_t *>(ck_s(w) + 2 * (size_t)n_ch); };
-  hipError_t e = hipMemcpyAsync(ck_z(0), sos->d_state, (size_t)(2 * K) * n_ch * sizeof(double),
-                                hipMemcpyDeviceToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ck_s(0), sl->d_state, 2 * (size_t)n_ch * sizeof(double), hipMemcpyDeviceToDevice, stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ck_c(0), sl->d_cnt, (size_t)n_ch * sizeof(int64_t), hipMemcpyDeviceToDevice, stream);
-  // forward states at the window starts
-  for (int64_t w = 0; w + 1 < n_win && e == hipSuccess; ++w) {
-    e = hipMemcpyAsync(ck_z(w + 1), ck_z(w), ck_doubles * sizeof(double), hipMemcpyDeviceToDevice, stream);
-    if (e == hipSuccess)
-      e = forward_launches(sos, sl, tf, ck_z(w + 1), ck_s(w + 1), ck_c(w + 1), x + (size_t)(w * rows) * n_ch,
-                           nullptr, nullptr, true, n_ch, rows, stream);
+  // window 0 starts from the objects' own state; slot w > 0 of the
+  // workspace holds the state at the start of window w.  A forward pass runs
+  // in place on the slot of its END (seeded with its start state), so the
+  // slot of its start stays intact.
+  const size_t z_bytes = (size_t)(2 * K) * n_ch * sizeof(double);
+  const size_t s_bytes = (size_t)n_ch * (2 * sizeof(double) + sizeof(int64_t));  // (sta, lta) then the counter
+  auto seed = [&](int64_t to, int64_t from) -> hipError_t {
+    if (from == 0) {
+      hipError_t r = hipMemcpyAsync(ck_z(to), sos->d_state, z_bytes, hipMemcpyDeviceToDevice, stream);
+      if (r == hipSuccess) r = hipMemcpyAsync(ck_s(to), sl->d_state, s_bytes, hipMemcpyDeviceToDevice, stream);
+      return r;
+    }
+    return hipMemcpyAsync(ck_z(to), ck_z(from), ck_doubles * sizeof(double), hipMemcpyDeviceToDevice, stream);
+  };
+  hipError_t e = hipSuccess;
+  // forward states at the window starts: one states-only pass over the rows
+  // before the last window, with 64-row blocks, writes them as it goes
+  // (windows that are a multiple of 64 rows and divide its 2048-row window);
+  // otherwise one states-only launch per window
+  const Tile tck = sos->ckp.tile;
+  const int64_t ck_win = tck.window();
+  const bool one_pass = rows % tck.block == 0 && ck_win % rows == 0 && launch_rows(tck, n_ch) != 0 &&
+                        sl->ckp.tile == tck &&
+                        check_lds(fwd_lds_bytes(K, tck.waves, tck.levels(), tck.group), tck, K, sos->device) ==
+                            FILARK_OK;
+  if (one_pass) {
+    const int64_t r_end = (n_win - 1) * rows;
+    for (int64_t t0 = 0; t0 < r_end && e == hipSuccess; t0 += ck_win) {
+      const int64_t nt = std::min(ck_win, r_end - t0);
+      const int64_t w0 = t0 / rows, w1 = (t0 + nt) / rows;
+      e = seed(w1, w0);
+      const CkSpec cks{ck_z(w0 + 1), (int64_t)ck_doubles, (int)rows};
+      if (e == hipSuccess)
+        e = forward_launches(sos, sl, tck, ck_z(w1), ck_s(w1), ck_c(w1), x + (size_t)t0 * n_ch, nullptr, nullptr,
+                             true, n_ch, nt, stream, false, &cks, true);
+    }
+  } else {
+    for (int64_t w = 0; w + 1 < n_win && e == hipSuccess; ++w) {
+      e = seed(w + 1, w);
+      if (e == hipSuccess)
+        e = forward_launches(sos, sl, tf, ck_z(w + 1), ck_s(w + 1), ck_c(w + 1), x + (size_t)(w * rows) * n_ch,
+                             nullptr, nullptr, true, n_ch, rows, stream);
+    }
   }
   // windows last to first
   AdjParams p;
@@ -935,6 +1020,9 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
   p.coef = sos->adj.d;
   p.G = sos->adj.d + sos->adj.off_G;
   p.Pw = sos->adj.d + sos->adj.off_P;
+  p.rinv = sos->adj.d + sos->adj.off_R;
+  p.first_order = sos->cas.first_order_bits();
+  p.recon = sos->cas.invertible() ? 1 : 0;
   p.dpow = sl->adj.d;
   p.cs = 1.0 / (double)sl->nsta;
   p.cl = 1.0 / (double)sl->nlta;
@@ -950,9 +1038,9 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
     p.gx = gx + off;
     p.n_t = (int32_t)nt;
     p.range = (int32_t)((uint64_t)nt * rowb);
-    p.zs0 = ck_z(w);
-    p.sl0 = ck_s(w);
-    p.cnt0 = ck_c(w);
+    p.zs0 = w == 0 ? sos->d_state : ck_z(w);
+    p.sl0 = w == 0 ? sl->d_state : ck_s(w);
+    p.cnt0 = w == 0 ? sl->d_cnt : ck_c(w);
     e = launch_adj(p, K, ta.block, sos->cas.unit_tail(), stream);
   }
   if (e == hipSuccess) e = launch_adj_reduce(sos->d_gpart, n_grp, 5 * K, gsos, stream);
@@ -1166,6 +1254,7 @@ filark_status filark_sos_destroy(filark_sos_t st) {
   if (st->d_state) (void)hipFree(st->d_state);
   if (st->fwd.d) (void)hipFree(st->fwd.d);
   if (st->adj.d) (void)hipFree(st->adj.d);
+  if (st->ckp.d) (void)hipFree(st->ckp.d);
   if (st->d_ck) (void)hipFree(st->d_ck);
   if (st->d_ff) (void)hipFree(st->d_ff);
   if (st->d_gpart) (void)hipFree(st->d_gpart);
@@ -1175,10 +1264,10 @@ filark_status filark_sos_destroy(filark_sos_t st) {
 
 filark_status filark_stalta_destroy(filark_stalta_t st) {
   if (!st) return FILARK_OK;
-  if (st->d_state) (void)hipFree(st->d_state);
-  if (st->d_cnt) (void)hipFree(st->d_cnt);
+  if (st->d_state) (void)hipFree(st->d_state);  // holds the counter too
   if (st->fwd.d) (void)hipFree(st->fwd.d);
   if (st->adj.d) (void)hipFree(st->adj.d);
+  if (st->ckp.d) (void)hipFree(st->ckp.d);
   delete st;
   return FILARK_OK;
 }

@@ -429,6 +429,17 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
     }
     lds_barrier();  // the capture below reuses the exchange
     {
+      // checkpoints of the filter state at every ck_blocks-th block start
+      // after the first (the adjoint's window starts)
+      kparams_t q = ps.get();
+      const int ckb = q->ck_blocks;
+      if (ckb > 0 && b > 0 && b % ckb == 0 && (int64_t)b * L < (int64_t)q->n_t && cval) {
+        double *ck = q->ck + (int64_t)(b / ckb - 1) * q->ck_stride;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) ck[i * n_ch + c] = z[i];
+      }
+    }
+    {
       kparams_t q = ps.get();
       const __amdgpu_buffer_rsrc_t ry =
           rsrc(WRITE_Y ? (const void *)q->y : (const void *)q->x, WRITE_Y ? q->out_range : 0);
@@ -481,6 +492,15 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
       Lin = xs[2 * (my - CW) + 1];
     }
     kparams_t q = ps.get();
+    {  // checkpoints of the STA/LTA state and the sample counter (as the filter's above)
+      const int ckb = q->ck_blocks;
+      if (ckb > 0 && b > 0 && b % ckb == 0 && (int64_t)b * L < (int64_t)q->n_t && cval) {
+        double *ck = q->ck + (int64_t)(b / ckb - 1) * q->ck_stride + (int64_t)NS * n_ch;
+        ck[c] = Sin / q->nsta_d;
+        ck[n_ch + c] = Lin / q->nlta_d;
+        reinterpret_cast<int64_t *>(ck + 2 * n_ch)[c] = g0 + row0;
+      }
+    }
     if (end_lane) {
       // sums after the last row, from the block entry and the partial block
       // sums kept at that row
@@ -492,6 +512,7 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
     }
     const int64_t jw = q->nlta - (g0 + row0);
     const int jwarm = jw <= 0 ? 0 : (jw >= L ? L : (int)jw);
+    if (q->out_range == 0) return;  // states only: no characteristic to write
     // past the warm-up for every row of the wave (a wave-uniform test): no
     // per-row comparison with the warm-up boundary
     if (g0 + (int64_t)w * R * L >= q->nlta)
@@ -534,12 +555,13 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   fwd_compute<K, L, STALTA, WRITE_Y, UNIT, REV, NT>(ps, g, xv);
 }
 
-// One channel group per workgroup.  Three waves per SIMD for 48- and 64-sample
-// blocks (at most 168 VGPRs), so that every workgroup of a 6000-channel chunk
-// is resident at once.
+// One channel group per workgroup.  At least three waves per SIMD for 48-
+// and 64-sample blocks (at most 168 VGPRs), four (128) for 48-sample blocks
+// of up to 4 sections, so that every workgroup of a 6000-channel chunk is
+// resident at once with the default 8-wave workgroups.
 template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV, bool NT>
-__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L >= 48 ? 3 : 1)))
-fwd_kernel(FwdParams) {
+__global__ void __launch_bounds__(kMaxWaves * kWave)
+__attribute__((amdgpu_waves_per_eu(L == 48 && K <= 4 ? 4 : (L >= 48 ? 3 : 1)))) fwd_kernel(FwdParams) {
   const PSrc ps{dev::kparams<FwdParams>()};
   const int g = group_of(ps.get()->per_xcd, ps.get()->order);
   if (g >= ps.get()->n_grp) return;  // whole workgroup, before any barrier

@@ -32,6 +32,13 @@ struct FwdParams {
   int32_t out_range;   // buffer range of y and cf: `range`, or 0 to write neither (states only)
   int32_t nt;          // 1: y and cf stores carry the non-temporal hint (groups of >= 16 channels)
   int32_t order;       // channel-group order within an XCD (dev::group_of)
+  // state checkpoints (for the adjoint): at the start of every ck_blocks-th
+  // block after the first, the filter state [2K][n_ch], the STA/LTA state
+  // [2][n_ch] and the sample counter [n_ch] (int64 in a double slot) go to
+  // ck + (i - 1) * ck_stride for the i-th such block; ck_blocks = 0: none
+  double *ck;
+  int64_t ck_stride;
+  int32_t ck_blocks;
 
   // SOS cascade
   double *zs;          // carried state [2K][n_ch], updated in place
@@ -70,6 +77,9 @@ struct AdjParams {
   double *adj;         // adjoint state [2K + 2][n_ch]: (u1, u2) per section, then sta, lta
   double *gpart;       // [n_grp][5K] coefficient-gradient sums of each group, added to
   const double *coef, *G, *Pw;  // forward tables (as FwdParams)
+  const double *rinv;  // [K]: 1 / (-a2), or 1 / (-a1) for a first-order section (rebuilding variant)
+  int32_t first_order; // bit k: section k is first order (a2 = b2 = 0)
+  int32_t recon;       // 1: section signals rebuilt backwards instead of stored (adj_kernel RECON)
   const double *dpow;           // [n_lev][2] decays^(L 2^k), then [L + 1][2] decays^m
   double asd, ald;     // 1 - 1/nsta, 1 - 1/nlta
   double cs, cl;       // 1/nsta, 1/nlta
