@@ -222,6 +222,24 @@ filark_status filark_tile_set(void *st, int kind, int block, int waves, int grou
 filark_status filark_tile_get(const void *st, int kind, int *block, int *waves, int *group);
 
 /*
+ * Tile autotuner: times the forward kernel of a scratch state with the same
+ * filter and channel count as `st` on a chunk of n_t rows of synthetic input
+ * (allocated and freed by the call) for each candidate tile, with HIP events
+ * on `stream`, takes the fastest and applies it to `st` (filark_tile_set).
+ *   block   0: search 32, 48 and 64; else keep this block (32, 48 or 64).
+ *   waves   0: search 2, 4 and 8 waves per workgroup; else keep this value.
+ *   groups  always searched: 4, 8, 16, 32 and 64 channels (those whose
+ *           window and LDS fit).
+ *   cache   a JSON file (or NULL): an entry for this shape (channels, rows,
+ *           sections, block and waves constraints) is applied without
+ *           measuring; a new measurement is added to the file.
+ * out_*: the tile chosen.  Synchronous.  Errors: FILARK_EINVAL (arguments,
+ * no candidate fits, cache not writable), FILARK_EHIP.
+ */
+filark_status filark_autotune(filark_sos_t st, int64_t n_t, int block, int waves, const char *cache,
+                              int *out_block, int *out_waves, int *out_group, hipStream_t stream);
+
+/*
  * Device-side checkpoints of a state (for the adjoint of a chunked run):
  * _bytes gives the size of the opaque device image, _save copies the state
  * into `dev_dst` and _load restores it from `dev_src` (device buffers of that
@@ -259,37 +277,41 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
                                         double *gsos, int64_t n_ch, int64_t n_t, hipStream_t stream);
 
 /*
- * Batched filtering of many independent streams in one launch sequence (the
- * stateful SOS operator of Section 3.4 applied to several records at once;
- * streams may differ in channel count, chunk length and filter).
+ * Batched filtering of many independent streams in one launch (the stateful
+ * SOS operator of Section 3.4 applied to several records at once; streams
+ * may differ in channel count, chunk length and filter).
  *   _create  takes n SOS state objects (one per stream; each keeps its own
- *            state and tables).  All must share the tile's block and waves;
- *            the channel group may differ per stream (per-stream tuning).
+ *            state and tables).  All must have 48-sample blocks and the same
+ *            waves per workgroup; the channel group may differ per stream
+ *            (per-stream tuning, e.g. with filark_autotune).
  *   _bind    records one chunk per stream: in[s], out[s] device FP32
  *            [n_t[s]][n_ch of state s] (host arrays of device pointers;
- *            n_t[s] = 0 skips the stream), builds the work tables and uploads
- *            them (synchronous).  Rebind when pointers or lengths change,
- *            and after filark_tile_set on any of the states (a launch after
- *            such a change fails with FILARK_EINVAL; bind refuses a state
- *            whose block or waves differ from the batch's).  A graph holding
- *            an earlier launch must be captured again after a bind: the
- *            work tables it names may have been reallocated.
- *   _launch  enqueues the bound work on `stream`: a fill kernel that clears
- *            the completion stamps, then one kernel per (window round,
- *            section count), each covering every stream of that kind.  The
- *            rounds of one section count form a chain; with more than one
- *            section count the chains run concurrently on streams the batch
- *            owns, forked from and joined back to `stream` by events, so the
- *            work is ordered after earlier work on `stream` and later work
- *            on `stream` follows it.  It allocates nothing and does not
- *            synchronise, so it may be captured in a HIP graph (the fork and
- *            join are captured with it); every launch or replay advances
- *            each stream's state by its chunk, exactly like
- *            filark_sos_process.  Launches of one batch must not overlap
- *            (they share the side streams and the stamps).
+ *            n_t[s] = 0 skips the stream), builds the work table and uploads
+ *            it (synchronous).  An item of work is one channel group of one
+ *            stream over every window of its chunk, walked in order by one
+ *            workgroup that carries the state from window to window; the
+ *            items sit in one queue per XCD (the groups of a stream in
+ *            contiguous slabs), longest first.  Rebind when pointers or
+ *            lengths change, and after filark_tile_set on any of the states
+ *            (a launch after such a change fails with FILARK_EINVAL; bind
+ *            refuses a state whose block or waves differ from the batch's).
+ *            A bind drops the graph held by _capture.
+ *   _launch  enqueues the bound work on `stream`: a reset kernel (queue
+ *            counters, completion stamps) and one persistent kernel whose
+ *            workgroups (as many as stay resident, at most the longest
+ *            queue) take items until their XCD's queue is empty; or, after
+ *            _capture, one launch of the captured graph.  It allocates
+ *            nothing and does not synchronise; every launch advances each
+ *            stream's state by its chunk, exactly like filark_sos_process
+ *            (bit for bit: the same kernel body and tile).  Launches of one
+ *            batch must not overlap (they share the counters and stamps).
+ *   _capture captures the launch sequence in a HIP graph owned by the batch
+ *            (on a stream of its own; synchronous); later _launch calls
+ *            replay it.  Callers that capture _launch into graphs of their
+ *            own must capture again after a bind.
  *   _stamps  synchronises `stream` and copies n + 1 uint64 values: the
- *            completion time of each stream's last workgroup and, last, the
- *            time the launch started, in ticks of the device's 100 MHz clock.
+ *            completion time of each stream's last item and, last, the time
+ *            the launch started, in ticks of the device's 100 MHz clock.
  * SOS only (no STA/LTA).  Errors as elsewhere; FILARK_EINVAL if a stream's
  * tile does not fit the device or the state objects disagree.
  */
@@ -297,6 +319,7 @@ filark_status filark_batch_create(filark_batch_t *b, int n, const filark_sos_t *
 filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float *const *out,
                                 const int64_t *n_t, hipStream_t stream);
 filark_status filark_batch_launch(filark_batch_t b, hipStream_t stream);
+filark_status filark_batch_capture(filark_batch_t b);
 filark_status filark_batch_stamps(filark_batch_t b, uint64_t *host, hipStream_t stream);
 filark_status filark_batch_destroy(filark_batch_t b);
 

@@ -33,7 +33,7 @@ EXPORTS = (
     "filark_check", "filark_sos_destroy", "filark_stalta_destroy", "filark_last_error",
     "filark_version", "filark_tile_set", "filark_tile_get", "filark_state_bytes", "filark_state_save",
     "filark_state_load", "filark_sos_stalta_adjoint", "filark_batch_create", "filark_batch_bind",
-    "filark_batch_launch", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
+    "filark_batch_launch", "filark_batch_capture", "filark_autotune", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
     "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
     "filark_sos_filtfilt", "filark_sos_filtfilt_noalloc", "filark_ema_init", "filark_ema_process", "filark_ema_state_get", "filark_ema_state_set",
     "filark_ema_destroy", "filark_fir_init", "filark_fir_set_tile", "filark_fir_process", "filark_fir_state_get",
@@ -84,6 +84,8 @@ def lib():
     L.filark_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), vp]
     L.filark_batch_bind.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64), vp]
     L.filark_batch_launch.argtypes = [vp, vp]
+    L.filark_batch_capture.argtypes = [vp]
+    L.filark_autotune.argtypes = [vp, i64, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ip, ip, ip, vp]
     L.filark_batch_stamps.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), vp]
     L.filark_batch_destroy.argtypes = [vp]
     L.filark_sos_destroy.argtypes = [vp]
@@ -393,6 +395,17 @@ def sos_stalta_adjoint(sos: SOSState, sl: StaLtaState, x, g, gx=None, adj=None, 
     return gx, adj, gsos
 
 
+def tune_tile(st: SOSState, n_t: int, block: int = 0, waves: int = 0, cache: str | None = None, stream=None):
+    """Time the tile candidates for st's filter and channel count on a chunk of
+    n_t rows (filark_autotune), apply the fastest to st and return it as
+    (block, waves, group); block / waves 0 are searched, else kept."""
+    b, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().filark_autotune(st.handle, int(n_t), int(block), int(waves),
+                                 cache.encode() if cache else None, ctypes.byref(b), ctypes.byref(w),
+                                 ctypes.byref(g), _stream(stream)))
+    return b.value, w.value, g.value
+
+
 class Batch:
     """Many independent SOS streams filtered by one launch sequence (see
     filark_batch_* in include/filark.h).  Each stream keeps its SOSState;
@@ -423,7 +436,12 @@ class Batch:
         self._bound = (list(xs), list(ys))  # keep the buffers alive while bound
 
     def launch(self, stream=None):
+        """One launch of the bound work (a replay of the captured graph after capture())."""
         _check(lib().filark_batch_launch(self._h, _stream(stream)))
+
+    def capture(self):
+        """Capture the launch sequence in a graph the batch owns; launch() then replays it."""
+        _check(lib().filark_batch_capture(self._h))
 
     def stamps(self, stream=None) -> np.ndarray:
         """Per-stream completion ticks and, last, the start tick (100 MHz)."""

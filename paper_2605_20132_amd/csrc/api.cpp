@@ -15,7 +15,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <mutex>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -55,6 +58,7 @@ filark_status fail(filark_status st, const char *fmt, ...) {
 // workgroups fill a CU with 12 waves, three on each SIMD: the VALU-bound
 // passes see no SIMD with more waves than the others.
 constexpr int kDefaultBlock = 48;
+constexpr int kBatchBlock = 48;  // the batched kernel's block length
 constexpr int kDefaultWaves = 8;
 constexpr int kDefaultGroup = 16;
 
@@ -223,22 +227,21 @@ struct filark_batch {
   int device = 0;
   std::vector<filark_sos_state *> st;
   std::vector<uint64_t> gen;  // each state's table generation when bound
-  int L = 0, nw = 0;
+  int nw = 0;                 // waves per workgroup (the states' common tile)
   FwdParams *d_descs = nullptr;
   size_t descs_bytes = 0;
   BatchItem *d_items = nullptr;
   size_t items_bytes = 0;
-  unsigned long long *d_stamps = nullptr;
-  struct Node {
-    int K, n_items, max_lev;
-    size_t item_off;
-  };
-  std::vector<Node> nodes;
+  uint32_t *d_heads = nullptr;              // [8] queue counters
+  unsigned long long *d_stamps = nullptr;   // [n + 1]
+  BatchParams bp{};
+  int kmax = 0, grid = 0;
+  size_t lds = 0;
   bool bound = false;
-  // one chain of kernels per section count runs on its own stream, forked
-  // from and joined back to the caller's stream by events
-  hipStream_t side[kMaxSections] = {};
-  hipEvent_t fork = nullptr, join[kMaxSections] = {};
+  // the launch sequence captured in a graph (filark_batch_capture)
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 struct filark_ema_state {
@@ -591,6 +594,13 @@ hipError_t filtfilt_launches(const filark_sos_state *sos, const float *in, float
   if (e == hipSuccess)
     e = forward_launches(sos, nullptr, t, work, nullptr, nullptr, out, out, nullptr, false, n_ch, n_t, stream, true);
   return e;
+}
+
+void drop_graph(filark_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
 }
 
 }  // namespace
@@ -1058,8 +1068,9 @@ filark_status filark_batch_create(filark_batch_t *out, int n, const filark_sos_t
   const Tile t0 = states[0]->fwd.tile;
   for (int i = 0; i < n; ++i) {
     if (states[i]->device != states[0]->device) return fail(FILARK_EINVAL, "states live on different devices");
-    if (states[i]->fwd.tile.block != t0.block || states[i]->fwd.tile.waves != t0.waves)
-      return fail(FILARK_EINVAL, "state %d: block and waves must match state 0's (group may differ)", i);
+    if (states[i]->fwd.tile.block != kBatchBlock || states[i]->fwd.tile.waves != t0.waves)
+      return fail(FILARK_EINVAL, "state %d: block must be %d and waves must match state 0's (group may differ)", i,
+                  kBatchBlock);
     for (int j = 0; j < i; ++j)
       if (states[j] == states[i]) return fail(FILARK_EINVAL, "state %d appears twice", i);
   }
@@ -1067,18 +1078,15 @@ filark_status filark_batch_create(filark_batch_t *out, int n, const filark_sos_t
   if (!b) return fail(FILARK_ENOMEM, "host allocation failed");
   b->device = states[0]->device;
   b->st.assign(states, states + n);
-  b->L = t0.block;
   b->nw = t0.waves;
   const int prev_dev = current_device();
   if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
   hipError_t e = hipMalloc(&b->d_stamps, (size_t)(n + 1) * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemsetAsync(b->d_stamps, 0, (size_t)(n + 1) * sizeof(unsigned long long), stream);
+  if (e == hipSuccess) e = hipMalloc(&b->d_heads, 8 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_heads, 0, 8 * sizeof(uint32_t), stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
-  for (int k = 0; k < kMaxSections && e == hipSuccess; ++k) {
-    e = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming);
-  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) {
     filark_batch_destroy(b);
@@ -1093,25 +1101,30 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
   if (!b || !in || !out || !n_t) return fail(FILARK_EINVAL, "null pointer");
   const int n = (int)b->st.size();
   std::vector<FwdParams> descs;
-  struct Win {
-    int s, K, desc, n_grp, n_lev;
-  };
-  std::vector<std::vector<Win>> rounds;
+  std::vector<BatchItem> lists[8];
+  int kmax = 1;
+  size_t lds = 0;
   for (int s = 0; s < n; ++s) {
     filark_sos_state *st = b->st[s];
     const Tile &t = st->fwd.tile;
-    if (t.block != b->L || t.waves != b->nw)
+    if (t.block != kBatchBlock || t.waves != b->nw)
       return fail(FILARK_EINVAL, "stream %d: block %d and waves %d differ from the batch's %d and %d", s, t.block,
-                  t.waves, b->L, b->nw);
+                  t.waves, kBatchBlock, b->nw);
     if (n_t[s] < 0) return fail(FILARK_EINVAL, "stream %d: negative n_t", s);
     if (n_t[s] > 0 && (!in[s] || !out[s])) return fail(FILARK_EINVAL, "stream %d: null pointer", s);
     const int64_t rows = launch_rows(t, st->n_ch);
     if (rows == 0) return fail(FILARK_EINVAL, "stream %d: n_ch too large for its tile", s);
     const int K = st->cas.K;
-    filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels(), kWave), t, K, b->device);
+    const size_t l = fwd_lds_bytes(K, t.waves, t.levels(), t.group);
+    filark_status rc = check_lds(l, t, K, b->device);
     if (rc != FILARK_OK) return rc;
+    if (n_t[s] == 0) continue;
+    kmax = std::max(kmax, K);
+    lds = std::max(lds, l);
     const uint64_t rowb = (uint64_t)st->n_ch * 4u;
-    for (int64_t t0 = 0, r = 0; t0 < n_t[s]; t0 += rows, ++r) {
+    const int desc0 = (int)descs.size();
+    const int n_grp = (int)((st->n_ch + t.group - 1) / t.group);
+    for (int64_t t0 = 0; t0 < n_t[s]; t0 += rows) {
       const int64_t nt = std::min(rows, n_t[s] - t0);
       FwdParams p;
       std::memset(&p, 0, sizeof p);
@@ -1122,8 +1135,8 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
       p.n_t = (int32_t)nt;
       p.cw_log2 = log2_exact(t.group);
       p.nw = t.waves;
-      p.n_grp = (int)((st->n_ch + t.group - 1) / t.group);
-      p.per_xcd = per_xcd_for(p.n_grp);
+      p.n_grp = n_grp;
+      p.per_xcd = per_xcd_for(n_grp);
       p.n_lev = t.levels();
       p.range = (int32_t)((uint64_t)nt * rowb);
       p.out_range = p.range;
@@ -1131,48 +1144,60 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
       p.coef = st->fwd.d;
       p.G = st->fwd.d + st->fwd.off_G;
       p.Pw = st->fwd.d + st->fwd.off_P;
-      if ((int64_t)rounds.size() <= r) rounds.resize(r + 1);
-      rounds[r].push_back({s, K, (int)descs.size(), p.n_grp, p.n_lev});
       descs.push_back(p);
     }
+    const int n_win = (int)descs.size() - desc0;
+    // groups dealt to the XCDs in contiguous slabs, so the groups that share
+    // cache lines meet in one L2
+    const int per = per_xcd_for(n_grp);
+    for (int g = 0; g < n_grp; ++g) lists[g / per].push_back({desc0, n_win, K, g, s, {0, 0, 0}});
   }
-  // items: per round and filter length, every XCD gets a contiguous slab of
-  // each stream's groups; workgroup i runs on XCD i % 8
+  // each queue longest items first (windows x sections): the last items to
+  // start are the shortest
   std::vector<BatchItem> items;
-  b->nodes.clear();
-  for (const auto &wins : rounds) {
-    for (int K = 1; K <= kMaxSections; ++K) {
-      std::vector<BatchItem> lists[8];
-      int max_lev = 0;
-      for (const Win &w : wins) {
-        if (w.K != K) continue;
-        max_lev = std::max(max_lev, w.n_lev);
-        const int per = per_xcd_for(w.n_grp);
-        for (int x = 0; x < 8; ++x)
-          for (int g = x * per; g < std::min(w.n_grp, (x + 1) * per); ++g) lists[x].push_back({w.desc, g, w.s, 0});
-      }
-      size_t len = 0;
-      for (auto &l : lists) len = std::max(len, l.size());
-      if (len == 0) continue;
-      const size_t off = items.size();
-      for (size_t i = 0; i < len; ++i)
-        for (int x = 0; x < 8; ++x) items.push_back(i < lists[x].size() ? lists[x][i] : BatchItem{-1, 0, 0, 0});
-      b->nodes.push_back({K, (int)(items.size() - off), max_lev, off});
-    }
+  int qoff[9] = {};
+  size_t longest = 0;
+  for (int x = 0; x < 8; ++x) {
+    std::stable_sort(lists[x].begin(), lists[x].end(), [](const BatchItem &u, const BatchItem &v) {
+      return (int64_t)u.n_win * (u.K + 2) > (int64_t)v.n_win * (v.K + 2);
+    });
+    qoff[x] = (int)items.size();
+    items.insert(items.end(), lists[x].begin(), lists[x].end());
+    longest = std::max(longest, lists[x].size());
   }
+  qoff[8] = (int)items.size();
   const int prev_dev = current_device();
   if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
-  HIP_TRY(hipStreamSynchronize(stream));
-  filark_status rc = grow_raw(&b->d_descs, &b->descs_bytes, std::max<size_t>(1, descs.size()) * sizeof(FwdParams));
-  if (rc == FILARK_OK) rc = grow_raw(&b->d_items, &b->items_bytes, std::max<size_t>(1, items.size()) * sizeof(BatchItem));
-  hipError_t e = hipSuccess;
-  if (rc == FILARK_OK && !descs.empty())
+  int per_cu = 0, n_cu = 0;
+  hipError_t e = batch_occupancy(kmax, b->nw, lds, &per_cu);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  drop_graph(b);
+  filark_status rc = FILARK_OK;
+  if (e == hipSuccess && per_cu < 1) rc = fail(FILARK_EINVAL, "the batch's tiles do not fit a CU");
+  if (rc == FILARK_OK && e == hipSuccess)
+    rc = grow_raw(&b->d_descs, &b->descs_bytes, std::max<size_t>(1, descs.size()) * sizeof(FwdParams));
+  if (rc == FILARK_OK && e == hipSuccess)
+    rc = grow_raw(&b->d_items, &b->items_bytes, std::max<size_t>(1, items.size()) * sizeof(BatchItem));
+  if (rc == FILARK_OK && e == hipSuccess && !descs.empty())
     e = hipMemcpy(b->d_descs, descs.data(), descs.size() * sizeof(FwdParams), hipMemcpyHostToDevice);
   if (rc == FILARK_OK && e == hipSuccess && !items.empty())
     e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
   if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
   if (rc != FILARK_OK) return rc;
   if (e != hipSuccess) return fail(FILARK_EHIP, "batch upload: %s", hipGetErrorString(e));
+  // as many workgroups as stay resident (a multiple of 8, one share per
+  // XCD), but no more than the longest queue needs
+  const int resident = std::max(1, per_cu * n_cu / 8);
+  b->grid = 8 * std::max(1, std::min(resident, (int)longest));
+  b->kmax = kmax;
+  b->lds = lds;
+  b->bp.descs = b->d_descs;
+  b->bp.items = b->d_items;
+  b->bp.heads = b->d_heads;
+  b->bp.stamps = b->d_stamps;
+  for (int x = 0; x < 9; ++x) b->bp.qoff[x] = qoff[x];
+  b->bp.n_streams = n;
   b->gen.resize(n);
   for (int s = 0; s < n; ++s) b->gen[s] = b->st[s]->gen;
   b->bound = true;
@@ -1187,35 +1212,35 @@ filark_status filark_batch_launch(filark_batch_t b, hipStream_t stream) {
       return fail(FILARK_EINVAL, "stream %zu: tile changed since filark_batch_bind; bind again", s);
   const int prev_dev = current_device();
   if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
-  hipError_t e = launch_stamp_reset(b->d_stamps, (int)b->st.size(), stream);
-  // Only the window rounds of one stream depend on each other, and the
-  // streams of one section count are launched together: the chains of
-  // different section counts run concurrently on the side streams.
-  bool present[kMaxSections] = {};
-  int chains = 0;
-  for (const auto &nd : b->nodes) {
-    chains += present[nd.K - 1] ? 0 : 1;
-    present[nd.K - 1] = true;
-  }
-  if (e == hipSuccess && chains > 1) e = hipEventRecord(b->fork, stream);
-  for (int K = 1; K <= kMaxSections && e == hipSuccess; ++K) {
-    if (!present[K - 1]) continue;
-    hipStream_t s = chains > 1 ? b->side[K - 1] : stream;
-    if (chains > 1) e = hipStreamWaitEvent(s, b->fork, 0);
-    for (const auto &nd : b->nodes) {  // rounds in order
-      if (e != hipSuccess) break;
-      if (nd.K != K) continue;
-      BatchParams bp;
-      bp.descs = b->d_descs;
-      bp.items = b->d_items + nd.item_off;
-      bp.stamps = b->d_stamps;
-      e = launch_fwd_batch(bp, nd.K, b->L, nd.n_items, b->nw, nd.max_lev, s);
-    }
-    if (e == hipSuccess && chains > 1) e = hipEventRecord(b->join[K - 1], s);
-    if (e == hipSuccess && chains > 1) e = hipStreamWaitEvent(stream, b->join[K - 1], 0);
-  }
+  const hipError_t e = b->exec ? hipGraphLaunch(b->exec, stream)
+                               : launch_fwd_batch(b->bp, b->kmax, b->grid, b->nw, b->lds, stream);
   if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "batch launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status filark_batch_capture(filark_batch_t b) {
+  if (!b) return fail(FILARK_EINVAL, "null batch");
+  if (!b->bound) return fail(FILARK_EINVAL, "batch not bound (filark_batch_bind)");
+  const int prev_dev = current_device();
+  if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
+  drop_graph(b);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    const hipError_t le = launch_fwd_batch(b->bp, b->kmax, b->grid, b->nw, b->lds, b->cap);
+    e = hipStreamEndCapture(b->cap, &g);
+    if (e == hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e == hipSuccess) {
+    b->graph = g;
+  } else if (g) {
+    (void)hipGraphDestroy(g);
+    b->exec = nullptr;
+  }
+  if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
+  if (e != hipSuccess) return fail(FILARK_EHIP, "batch capture failed: %s", hipGetErrorString(e));
   return FILARK_OK;
 }
 
@@ -1228,15 +1253,134 @@ filark_status filark_batch_stamps(filark_batch_t b, uint64_t *host, hipStream_t 
 
 filark_status filark_batch_destroy(filark_batch_t b) {
   if (!b) return FILARK_OK;
+  drop_graph(b);
   if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_items) (void)hipFree(b->d_items);
   if (b->d_stamps) (void)hipFree(b->d_stamps);
-  for (int k = 0; k < kMaxSections; ++k) {
-    if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
-    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
-  }
-  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->d_heads) (void)hipFree(b->d_heads);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   delete b;
+  return FILARK_OK;
+}
+
+filark_status filark_autotune(filark_sos_t st, int64_t n_t, int block, int waves, const char *cache,
+                              int *out_block, int *out_waves, int *out_group, hipStream_t stream) {
+  if (!st || !out_block || !out_waves || !out_group) return fail(FILARK_EINVAL, "null pointer");
+  if (n_t < 1 || n_t > ((int64_t)1 << 31)) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
+  if (block != 0 && block != 32 && block != 48 && block != 64)
+    return fail(FILARK_EINVAL, "block must be 0 (search) or 32, 48, 64");
+  if (waves < 0 || waves > kMaxWaves) return fail(FILARK_EINVAL, "waves must be 0 (search) or 1 .. %d", kMaxWaves);
+  const int64_t n_ch = st->n_ch;
+  const int K = st->cas.K;
+  char key[160];
+  std::snprintf(key, sizeof key, "n_ch=%lld n_t=%lld K=%d block=%d waves=%d", (long long)n_ch, (long long)n_t, K,
+                block, waves);
+  // the cache: one entry per line, "key": {"block": B, "waves": W, "group": G, "us": T}
+  std::map<std::string, std::string> entries;
+  if (cache) {
+    std::ifstream f(cache);
+    std::string line;
+    while (std::getline(f, line)) {
+      const size_t q0 = line.find('"'), q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+      const size_t b0 = line.find('{'), b1 = line.rfind('}');
+      if (q1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos || b1 < b0) continue;
+      entries[line.substr(q0 + 1, q1 - q0 - 1)] = line.substr(b0, b1 - b0 + 1);
+    }
+    auto it = entries.find(key);
+    int cb = 0, cw = 0, cg = 0;
+    if (it != entries.end() &&
+        std::sscanf(it->second.c_str(), "{\"block\": %d, \"waves\": %d, \"group\": %d", &cb, &cw, &cg) == 3 &&
+        check_tile(cb, cw, cg, false) == FILARK_OK) {
+      filark_status rc = filark_tile_set(st, FILARK_STATE_SOS, cb, cw, cg, stream);
+      if (rc != FILARK_OK) return rc;
+      *out_block = cb;
+      *out_waves = cw;
+      *out_group = cg;
+      return FILARK_OK;
+    }
+  }
+  // a scratch state of the same filter, and synthetic input of the shape
+  std::vector<double> sos(6 * (size_t)K);
+  for (int k = 0; k < K; ++k) {
+    const double *c = st->cas.c[k];
+    const double row[6] = {c[0], c[1], c[2], 1.0, c[3], c[4]};
+    std::copy(row, row + 6, sos.begin() + 6 * k);
+  }
+  const int prev_dev = current_device();
+  if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));
+  filark_sos_t tmp = nullptr;
+  filark_status rc = filark_sos_init(&tmp, sos.data(), K, n_ch, 0, stream);
+  float *buf = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
+  const size_t bytes = (size_t)n_t * (size_t)n_ch * sizeof(float);
+  if (rc == FILARK_OK) e = hipMalloc(&buf, 2 * bytes);
+  if (rc == FILARK_OK && e == hipSuccess) e = hipMemsetAsync(buf, 0, 2 * bytes, stream);
+  if (rc == FILARK_OK && e == hipSuccess) e = hipEventCreate(&e0);
+  if (rc == FILARK_OK && e == hipSuccess) e = hipEventCreate(&e1);
+  const std::vector<int> blocks = block ? std::vector<int>{block} : std::vector<int>{32, 48, 64};
+  const std::vector<int> wave_set = waves ? std::vector<int>{waves} : std::vector<int>{2, 4, 8};
+  const int groups[5] = {4, 8, 16, 32, 64};
+  constexpr int kReps = 3;
+  float best = -1.0f;
+  int bb = 0, bw = 0, bg = 0;
+  for (const int blk : blocks) {
+    for (const int wv : wave_set) {
+      for (int ig = 0; ig < 5 && rc == FILARK_OK && e == hipSuccess; ++ig) {
+        Tile t;
+        t.block = blk;
+        t.waves = wv;
+        t.group = groups[ig];
+        if (t.blocks() < 1 || launch_rows(t, n_ch) == 0) continue;
+        if (check_lds(fwd_lds_bytes(K, t.waves, t.levels(), t.group), t, K, st->device) != FILARK_OK) continue;
+        rc = filark_tile_set(tmp, FILARK_STATE_SOS, t.block, t.waves, t.group, stream);
+        if (rc != FILARK_OK) break;
+        rc = filark_sos_process(tmp, buf, buf + bytes / sizeof(float), n_ch, n_t, stream);  // warm-up
+        if (rc != FILARK_OK) break;
+        e = hipEventRecord(e0, stream);
+        for (int r = 0; r < kReps && rc == FILARK_OK && e == hipSuccess; ++r)
+          rc = filark_sos_process(tmp, buf, buf + bytes / sizeof(float), n_ch, n_t, stream);
+        if (rc == FILARK_OK && e == hipSuccess) e = hipEventRecord(e1, stream);
+        if (rc == FILARK_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (rc == FILARK_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rc == FILARK_OK && e == hipSuccess && (best < 0.0f || ms < best)) {
+          best = ms;
+          bb = t.block;
+          bw = t.waves;
+          bg = t.group;
+        }
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (buf) (void)hipFree(buf);
+  if (tmp) filark_sos_destroy(tmp);
+  if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
+  if (rc != FILARK_OK) return rc;
+  if (e != hipSuccess) return fail(FILARK_EHIP, "autotune: %s", hipGetErrorString(e));
+  if (best < 0.0f) return fail(FILARK_EINVAL, "no tile candidate fits %lld channels", (long long)n_ch);
+  rc = filark_tile_set(st, FILARK_STATE_SOS, bb, bw, bg, stream);
+  if (rc != FILARK_OK) return rc;
+  *out_block = bb;
+  *out_waves = bw;
+  *out_group = bg;
+  if (cache) {
+    char val[128];
+    std::snprintf(val, sizeof val, "{\"block\": %d, \"waves\": %d, \"group\": %d, \"us\": %.2f}", bb, bw, bg,
+                  1e3 * best / kReps);
+    entries[key] = val;
+    const std::string tmp_path = std::string(cache) + ".tmp";
+    std::ofstream f(tmp_path);
+    f << "{\n";
+    size_t i = 0;
+    for (const auto &kv : entries) f << " \"" << kv.first << "\": " << kv.second << (++i < entries.size() ? ",\n" : "\n");
+    f << "}\n";
+    f.close();
+    if (!f || std::rename(tmp_path.c_str(), cache) != 0)
+      return fail(FILARK_EINVAL, "autotune: cannot write the cache %s", cache);
+  }
   return FILARK_OK;
 }
 

@@ -19,71 +19,122 @@ size_t fwd_lds_bytes(int K, int nw, int n_lev, int cw) {
 
 namespace {
 
-// Batched launch: workgroup i runs item i of a host-built table, a channel
-// group of one stream's window (its descriptor), or nothing (padding).  Items
-// are laid out so that XCD i % 8 holds a contiguous slab of every stream's
-// groups.  At its end each workgroup raises its stream's completion stamp
-// (the device's 100 MHz clock) with an atomic max.
-template <int K, int L>
-__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(L >= 48 ? 3 : 1)))
-fwd_batch_kernel(BatchParams) {
-  const FILARK_CONST BatchParams *bp = dev::kparams<BatchParams>();
-  const FILARK_CONST BatchItem *it = (const FILARK_CONST BatchItem *)bp->items + blockIdx.x;
-  const int desc = it->desc;
-  if (desc < 0) return;  // padding, whole workgroup
-  const PSrc ps{(kparams_t)(bp->descs + desc)};
-  fwd_body<K, L, false, true, false, false, false>(ps, it->group);
-  unsigned long long *stamps = bp->stamps;
-  if (stamps) {
-    __syncthreads();  // every wave's stores have completed
-    if (threadIdx.x == 0) atomicMax(stamps + it->stream, (unsigned long long)__builtin_amdgcn_s_memrealtime());
-  }
-}
-
-// Clear the completion stamps of n streams and record the start stamp in
-// slot n (a fill kernel, so the reset can live in a captured graph).
-__global__ void __launch_bounds__(256) stamp_reset_kernel(unsigned long long *stamps, int n) {
+// Reset of a batched launch: the queue counters, the stream stamps, and the
+// start stamp in slot n (a kernel, so the reset replays correctly in a graph).
+__global__ void __launch_bounds__(256) batch_reset_kernel(uint32_t *heads, unsigned long long *stamps, int n) {
+  if (threadIdx.x < 8) heads[threadIdx.x] = 0u;
   for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) stamps[i] = 0ull;
   if (threadIdx.x == 0) stamps[n] = (unsigned long long)__builtin_amdgcn_s_memrealtime();
 }
 
-template <int K, int L>
-hipError_t launch_batch_k(const BatchParams &bp, int n_items, int nw, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL((fwd_batch_kernel<K, L>), dim3((unsigned)n_items), dim3((unsigned)(nw * kWave)), lds,
-                     stream, bp);
+// One item: channel group g of one stream, its windows in order.  The state a
+// window's last-row lanes write is read by the next window's first-block
+// lanes, other waves of this workgroup: the release / acquire fences at
+// workgroup scope around the barrier order those global accesses (the
+// workgroup's waves share one L1).
+template <int K>
+__device__ __forceinline__ void batch_walk(const FILARK_CONST BatchParams *bp, const FILARK_CONST BatchItem *it) {
+  const int desc0 = it->desc0, n_win = it->n_win, g = it->group;
+  for (int w = 0; w < n_win; ++w) {
+    const PSrc ps{(kparams_t)(bp->descs + desc0 + w)};
+    fwd_body<K, 48, false, true, false, false, false>(ps, g);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+}
+
+// The persistent batched kernel for cascades of up to KMAX sections (the
+// registers are those of the largest cascade compiled in, so the host picks
+// the smallest KMAX that covers its streams).  Every workgroup leaves when
+// its XCD's queue is empty.
+template <int KMAX>
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(3)))
+fwd_batch_kernel(BatchParams) {
+  const FILARK_CONST BatchParams *bp = dev::kparams<BatchParams>();
+  __shared__ int next;
+  const int x = (int)blockIdx.x & 7;
+  const int q0 = bp->qoff[x], q1 = bp->qoff[x + 1];
+  const bool wave0 = uniform((int)(threadIdx.x / kWave)) == 0;  // a scalar branch
+  const bool lane0 = (threadIdx.x & (kWave - 1)) == 0;
+  // The loop holds no lane-divergent branch: one around the barriers of a
+  // loop lets the compiler split it into nested loops in which the waves can
+  // come back to the barriers without taking a new item.  So the whole of
+  // wave 0 takes the next item (lane 0 adds 1, the others 0) and every lane
+  // of it writes the same index.
+  for (;;) {
+    if (wave0) {
+      const uint32_t old = atomicAdd(bp->heads + x, lane0 ? 1u : 0u);
+      next = q0 + (int)__builtin_amdgcn_readfirstlane((int)old);
+    }
+    __syncthreads();
+    const int i = uniform(next);
+    __syncthreads();  // every wave has read `next` before it is written again
+    if (i >= q1) break;  // the whole workgroup: i is uniform
+    const FILARK_CONST BatchItem *it = (const FILARK_CONST BatchItem *)bp->items + i;
+    switch (it->K) {
+      case 1: batch_walk<1>(bp, it); break;
+      case 2: if constexpr (KMAX >= 2) batch_walk<2>(bp, it); break;
+      case 3: if constexpr (KMAX >= 3) batch_walk<3>(bp, it); break;
+      case 4: if constexpr (KMAX >= 4) batch_walk<4>(bp, it); break;
+      case 5: if constexpr (KMAX >= 5) batch_walk<5>(bp, it); break;
+      case 6: if constexpr (KMAX >= 6) batch_walk<6>(bp, it); break;
+      case 7: if constexpr (KMAX >= 7) batch_walk<7>(bp, it); break;
+      case 8: if constexpr (KMAX >= 8) batch_walk<8>(bp, it); break;
+      default: break;
+    }
+    // batch_walk ends on a barrier: every wave's stores of the item are done
+    if (wave0) {
+      const unsigned long long now = __builtin_amdgcn_s_memrealtime();
+      atomicMax(bp->stamps + it->stream, lane0 ? now : 0ull);
+    }
+  }
+}
+
+template <int KMAX>
+hipError_t launch_batch_k(const BatchParams &bp, int grid, int nw, size_t lds, hipStream_t stream) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, stream, bp.heads, bp.stamps, bp.n_streams);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((fwd_batch_kernel<KMAX>), dim3((unsigned)grid), dim3((unsigned)(nw * kWave)), lds, stream, bp);
   return hipGetLastError();
 }
 
-template <int L>
-hipError_t launch_batch_l(const BatchParams &bp, int K, int n_items, int nw, size_t lds, hipStream_t stream) {
-  switch (K) {
-    case 1: return launch_batch_k<1, L>(bp, n_items, nw, lds, stream);
-    case 2: return launch_batch_k<2, L>(bp, n_items, nw, lds, stream);
-    case 3: return launch_batch_k<3, L>(bp, n_items, nw, lds, stream);
-    case 4: return launch_batch_k<4, L>(bp, n_items, nw, lds, stream);
-    case 5: return launch_batch_k<5, L>(bp, n_items, nw, lds, stream);
-    case 6: return launch_batch_k<6, L>(bp, n_items, nw, lds, stream);
-    case 7: return launch_batch_k<7, L>(bp, n_items, nw, lds, stream);
-    case 8: return launch_batch_k<8, L>(bp, n_items, nw, lds, stream);
-    default: return hipErrorInvalidValue;
-  }
+template <int KMAX>
+hipError_t occupancy_k(int nw, size_t lds, int *per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void *>(&fwd_batch_kernel<KMAX>),
+                                                      nw * kWave, lds);
 }
 
 }  // namespace
 
-hipError_t launch_fwd_batch(const BatchParams &bp, int K, int L, int n_items, int nw, int max_lev,
-                            hipStream_t stream) {
-  if (n_items < 1 || nw < 1 || nw > kMaxWaves || max_lev < 1 || max_lev > kMaxLevels) return hipErrorInvalidValue;
-  const size_t lds = fwd_lds_bytes(K, nw, max_lev, kWave);  // any stream's group
-  if (L == 32) return launch_batch_l<32>(bp, K, n_items, nw, lds, stream);
-  if (L == 48) return launch_batch_l<48>(bp, K, n_items, nw, lds, stream);
-  if (L == 64) return launch_batch_l<64>(bp, K, n_items, nw, lds, stream);
-  return hipErrorInvalidValue;
+hipError_t launch_fwd_batch(const BatchParams &bp, int kmax, int grid, int nw, size_t lds, hipStream_t stream) {
+  if (grid < 1 || nw < 1 || nw > kMaxWaves) return hipErrorInvalidValue;
+  switch (kmax) {
+    case 1: return launch_batch_k<1>(bp, grid, nw, lds, stream);
+    case 2: return launch_batch_k<2>(bp, grid, nw, lds, stream);
+    case 3: return launch_batch_k<3>(bp, grid, nw, lds, stream);
+    case 4: return launch_batch_k<4>(bp, grid, nw, lds, stream);
+    case 5: return launch_batch_k<5>(bp, grid, nw, lds, stream);
+    case 6: return launch_batch_k<6>(bp, grid, nw, lds, stream);
+    case 7: return launch_batch_k<7>(bp, grid, nw, lds, stream);
+    case 8: return launch_batch_k<8>(bp, grid, nw, lds, stream);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_stamp_reset(unsigned long long *stamps, int n, hipStream_t stream) {
-  hipLaunchKernelGGL(stamp_reset_kernel, dim3(1), dim3(256), 0, stream, stamps, n);
-  return hipGetLastError();
+hipError_t batch_occupancy(int kmax, int nw, size_t lds, int *per_cu) {
+  switch (kmax) {
+    case 1: return occupancy_k<1>(nw, lds, per_cu);
+    case 2: return occupancy_k<2>(nw, lds, per_cu);
+    case 3: return occupancy_k<3>(nw, lds, per_cu);
+    case 4: return occupancy_k<4>(nw, lds, per_cu);
+    case 5: return occupancy_k<5>(nw, lds, per_cu);
+    case 6: return occupancy_k<6>(nw, lds, per_cu);
+    case 7: return occupancy_k<7>(nw, lds, per_cu);
+    case 8: return occupancy_k<8>(nw, lds, per_cu);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, bool rev,

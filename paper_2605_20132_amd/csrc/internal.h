@@ -123,16 +123,29 @@ struct EmaParams {
 
 hipError_t launch_ema(const EmaParams &p, int L, hipStream_t stream);
 
-// Batched forward launch (SOS only): workgroup i runs items[i], a channel
-// group of the window described by descs[desc] (desc < 0: padding), and
-// raises stamps[stream] to its completion time.
+// Batched forward launch (SOS only), one persistent kernel: an item is one
+// channel group of one stream over every window of that stream's chunk (the
+// consecutive descriptors descs[desc0 .. desc0 + n_win)), walked in order by
+// one workgroup, which carries the state from window to window.  Items sit in
+// 8 queues, one per XCD (queue x = items[qoff[x] .. qoff[x + 1])); the
+// workgroups on XCD x take them in order from an atomic counter heads[x]
+// until the queue is empty.  At the end of an item the workgroup raises
+// stamps[stream] to its completion time.
 struct BatchItem {
-  int32_t desc, group, stream, pad;
+  int32_t desc0;   // descriptor of the first window
+  int32_t n_win;   // windows
+  int32_t K;       // sections
+  int32_t group;   // channel group
+  int32_t stream;
+  int32_t pad[3];
 };
 struct BatchParams {
   const FwdParams *descs;
   const BatchItem *items;
-  unsigned long long *stamps;  // [n_streams + 1] or nullptr
+  uint32_t *heads;             // [8] queue counters, zeroed before each launch
+  unsigned long long *stamps;  // [n_streams + 1]: completion stamps, then the start stamp
+  int32_t qoff[9];
+  int32_t n_streams;
 };
 
 // Dynamic LDS bytes of a forward workgroup.
@@ -150,12 +163,12 @@ hipError_t launch_fwd_l64(const FwdParams &p, int K, bool stalta, bool write_y, 
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, bool rev,
                       hipStream_t stream);
 
-// Batched launch of n_items workgroups of nw waves for K sections and
-// L-sample blocks (max_lev: the most scan levels among the descriptors), and
-// the fill kernel that clears n completion stamps and records the start.
-hipError_t launch_fwd_batch(const BatchParams &bp, int K, int L, int n_items, int nw, int max_lev,
-                            hipStream_t stream);
-hipError_t launch_stamp_reset(unsigned long long *stamps, int n, hipStream_t stream);
+// Batched launch: the reset kernel (queue counters and stamps) and the
+// persistent kernel, grid workgroups of nw waves with lds bytes of dynamic
+// LDS, for cascades of up to kmax sections and 48-row blocks.  The occupancy
+// query gives the workgroups of that kernel resident per CU.
+hipError_t launch_fwd_batch(const BatchParams &bp, int kmax, int grid, int nw, size_t lds, hipStream_t stream);
+hipError_t batch_occupancy(int kmax, int nw, size_t lds, int *per_cu);
 
 // Channel groups per XCD slab and workgroups launched for n_grp groups.
 inline int per_xcd_for(int n_grp) { return (n_grp + 7) / 8; }

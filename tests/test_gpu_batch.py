@@ -39,7 +39,7 @@ STREAMS = [
 ]
 
 
-def _make(F, orc, block=64, waves=4):
+def _make(F, orc, block=48, waves=4):
     sts, soss = [], []
     for n_ch, n_t, order, f1, f2, fs, group in STREAMS:
         sos = orc.butter_sos(order, "bandpass", f1, f2, fs)
@@ -147,17 +147,102 @@ def test_batch_argument_errors(F):
     assert e.value.status == F.ESHAPE
 
 
-def test_autotuner_picks_and_caches(F, tmp_path):
-    from paper_2605_20132_amd.autotune import GROUPS, Autotuner
+def test_autotuner_picks_applies_and_caches(F, tmp_path):
+    """filark_autotune through the Python caller: the chosen tile is applied
+    to the state, written to the JSON cache and reused from it."""
+    import json
+
+    from paper_2605_20132_amd.autotune import Autotuner
 
     orc = _orc()
     sos = orc.butter_sos(4, "bandpass", 1.0, 50.0, 500.0)
     path = str(tmp_path / "tiles.json")
-    t = Autotuner(path, block=64, waves=4, reps=2)
-    gsel = t.group_for(sos, 3000, 1000)
-    assert gsel in GROUPS
-    t2 = Autotuner(path, block=64, waves=4)
-    assert t2.group_for(sos, 3000, 1000) == gsel  # from the cache, no measurement
+    st = F.SOSState(sos, 3000)
+    block, waves, group = Autotuner(path, block=48, waves=4).tune(st, 1000)
+    assert (block, waves) == (48, 4) and group in (4, 8, 16, 32, 64)
+    assert st.tile() == (block, waves, group)
+    table = json.load(open(path))
+    assert len(table) == 1 and list(table.values())[0]["group"] == group
+    # a free search (block and waves too) adds an entry of its own
+    b2, w2, g2 = F.tune_tile(st, 1000, cache=path)
+    assert b2 in (32, 48, 64) and w2 in (2, 4, 8) and st.tile() == (b2, w2, g2)
+    assert len(json.load(open(path))) == 2
+    st2 = F.SOSState(sos, 3000)
+    assert Autotuner(path, block=48, waves=4).tune(st2, 1000) == (block, waves, group)  # from the cache
+    assert st2.tile() == (block, waves, group)
+    st.close()
+    st2.close()
+
+
+def test_batch_capture_replays(F):
+    """The batch-owned graph (filark_batch_capture): each launch after the
+    capture replays it, with eager work in between, and must equal the
+    per-stream calls on objects advanced the same way; a bind drops it."""
+    orc = _orc()
+    sts, _ = _make(F, orc)
+    ref_sts, _ = _make(F, orc)
+    xs = _inputs(30)
+    ys = [torch.empty_like(x) for x in xs]
+    b = F.Batch(sts)
+    b.bind(xs, ys)
+    b.capture()
+    for rep in range(3):
+        b.launch()
+        refs = [st.process(x) for st, x in zip(ref_sts, xs)]
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for i, (y, r) in enumerate(zip(ys, refs)):
+            assert torch.equal(y, r), f"replay {rep}: stream {i} differs"
+    xs2 = _inputs(31)
+    ys2 = [torch.empty_like(x) for x in xs2]
+    b.bind(xs2, ys2)  # drops the graph: the next launch runs the new binding
+    b.launch()
+    refs = [st.process(x) for st, x in zip(ref_sts, xs2)]
+    torch.cuda.synchronize()
+    for y, r in zip(ys2, refs):
+        assert torch.equal(y, r)
+
+
+def test_drawn_twelve_stream_table_against_oracle(F):
+    """The uneven 12-stream table of the batched benchmark (channel counts
+    500 .. 20,000, rates 100 Hz .. 10 kHz, chunks 0.25-2 s, orders 2-10), each
+    stream's group chosen by the autotuner, two chunks in a row through one
+    captured batch: sampled channels of every stream (first, middle, last and
+    five drawn) against the oracle run over both chunks."""
+    import synth
+    from paper_2605_20132_amd.autotune import Autotuner
+
+    orc = _orc()
+    specs = synth.draw_batched_streams()
+    tuner = Autotuner(None, block=48, waves=8)
+    sts, soss, xs1, xs2 = [], [], [], []
+    for sp in specs:
+        sos = orc.butter_sos(sp.order, "bandpass", sp.f1, sp.f2, sp.fs)
+        st = F.SOSState(sos, sp.n_ch)
+        tuner.tune(st, sp.n_t)
+        sts.append(st)
+        soss.append(sos)
+        xs1.append(synth.pink_noise(sp.n_t, sp.n_ch, seed=sp.seed, device="cuda"))
+        xs2.append(synth.pink_noise(sp.n_t, sp.n_ch, seed=sp.seed + 7, device="cuda"))
+    ys1 = [torch.empty_like(x) for x in xs1]
+    ys2 = [torch.empty_like(x) for x in xs2]
+    b1, b2 = F.Batch(sts), F.Batch(sts)
+    b1.bind(xs1, ys1)
+    b2.bind(xs2, ys2)
+    b1.capture()
+    b2.capture()
+    b1.launch()
+    b2.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    for i, (sp, sos) in enumerate(zip(specs, soss)):
+        cols = sorted(set([0, sp.n_ch // 2, sp.n_ch - 1] + list(rng.integers(0, sp.n_ch, 5))))
+        x = torch.cat([xs1[i][:, cols], xs2[i][:, cols]]).double().cpu().numpy()
+        y = torch.cat([ys1[i][:, cols], ys2[i][:, cols]]).double().cpu().numpy()
+        yo, _ = orc.sos_filter(sos, x)
+        err = max_rel_rms(y, yo)
+        assert err <= tolerance_for(sos), (i, sp, err)
 
 
 def test_tile_change_after_bind_is_refused_until_bound_again(F):
@@ -172,13 +257,13 @@ def test_tile_change_after_bind_is_refused_until_bound_again(F):
     b.bind(xs, ys)
     b.launch()
     torch.cuda.synchronize()
-    sts[1].set_tile(64, 4, 8)  # group only: allowed per stream, but the tables are new
+    sts[1].set_tile(48, 4, 8 if STREAMS[1][6] != 8 else 16)  # group only: allowed per stream, but new tables
     with pytest.raises(F.FilarkError):
         b.launch()
     b.bind(xs, ys)
     b.launch()
     torch.cuda.synchronize()
-    sts[2].set_tile(48, 4, 16)  # block differs from the batch's
+    sts[2].set_tile(64, 4, 16)  # block differs from the batch's
     with pytest.raises(F.FilarkError):
         b.bind(xs, ys)
     b.close()
