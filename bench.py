@@ -379,7 +379,74 @@ def fir_leg(F, torch, dev, steps: int, parity: bool):
         log(f"[bench] FIR parity on {len(cols)} channels: max error / bound {worst:.3f}")
         f2.close()
     f.close()
+    res["long_taps"] = [fir_fft_case(F, torch, dev, x, w.chunk, Ml, steps, parity) for Ml in (256, 1024)]
     return res
+
+
+def fir_fft_case(F, torch, dev, x, chunk, M, steps, parity):
+    """One long lowpass over the same record in chunks: the direct method
+    against FFT filtering (2048-row overlap-save windows).  The FFT's
+    algorithmic traffic is the direct form's, 8 B per channel-sample (its
+    window overlap re-reads (M - 1) / (2049 - M) of the input from L2)."""
+    import numpy as np
+
+    n_t, n_ch = x.shape
+    h = fir_taps(M)
+    y = torch.empty_like(x)
+    out = {"taps": M}
+    for method in ("direct", "fft"):
+        f = F.Fir(h, n_ch)
+        f.set_method(method)
+
+        def run():
+            for a in range(0, n_t, chunk):
+                f.process(x[a:a + chunk], y[a:a + chunk])
+
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        gbs = n_t * n_ch * 8 / (ms / 1e3) / 1e9
+        out[method] = {"ms_per_step": ms, "value": n_t * n_ch / (ms / 1e3), "unit": "channel-samples/s",
+                       "algorithmic_gbs": gbs, "hbm_frac": gbs / 8000.0}
+        if method == "direct":
+            out[method]["tflops"] = n_t * n_ch * 2 * M / (ms / 1e3) / 1e12
+        if method == "fft" and parity:
+            import oracle
+
+            # sampled channels of the whole record in chunks, against the
+            # oracle: per block, ||err||_2 <= 156 u max|H| ||window||_2 (the
+            # FFT bound the GPU tests check block by block); summed over the
+            # blocks, whose windows cover every row 2048 / (2049 - M) times,
+            # RMS err <= 156 sqrt(2048 / (2049 - M)) u max|H| RMS x
+            f2 = F.Fir(h, n_ch)
+            f2.set_method("fft")
+            for a in range(0, n_t, chunk):
+                f2.process(x[a:a + chunk], y[a:a + chunk])
+            torch.cuda.synchronize()
+            cols = np.random.default_rng(15).choice(n_ch, 8, replace=False)
+            tc = torch.as_tensor(cols, device=dev)
+            xs = x[:, tc].double().cpu().numpy()
+            h32 = h.astype(np.float32).astype(np.float64)
+            yo = oracle.Fir(h32, len(cols)).process(xs)
+            yg = y[:, tc].double().cpu().numpy()
+            maxH = float(np.max(np.abs(np.fft.fft(h32, 2048))))
+            rel = float(np.max(np.sqrt(np.mean((yg - yo) ** 2, axis=0)) /
+                               (2.0 ** -24 * maxH * np.sqrt(np.mean(xs * xs, axis=0)))))
+            bound = float(156.0 * np.sqrt(2048.0 / (2049 - M)))
+            out[method]["parity"] = {"channels": len(cols), "rms_err_over_u_maxH_rms_x": rel, "bound": bound,
+                                     "ok": rel <= bound}
+            f2.close()
+        f.close()
+    out["fft_speedup"] = out["direct"]["ms_per_step"] / out["fft"]["ms_per_step"]
+    log(f"[bench] FIR {M} taps: direct {out['direct']['ms_per_step']:.3f} ms, fft {out['fft']['ms_per_step']:.3f} ms "
+        f"({out['fft']['algorithmic_gbs']:.0f} GB/s), speed-up {out['fft_speedup']:.2f}")
+    return out
 
 
 def trigger_leg(F, torch, dev, steps: int, parity: bool):

@@ -380,6 +380,24 @@ filark_status filark_ema_destroy(filark_ema_t st);
  * FILARK_EHIP.
  */
 filark_status filark_fir_init(filark_fir_t *st, const double *taps, int n_taps, int64_t n_ch, hipStream_t stream);
+/*
+ * Method of a FIR object: FILARK_FIR_DIRECT (the default: direct form, FP32
+ * FMAs in ascending tap order, chunked == one-shot bit for bit) or
+ * FILARK_FIR_FFT (FFT filtering, Table 1's overlap-add row: blocks of
+ * 2049 - n_taps output rows, each the last rows of a 2048-row window's
+ * circular convolution with the zero-padded taps (overlap-save, which sums
+ * the same products as overlap-add and carries the same input history as the
+ * direct form), in FP32 radix-4 transforms of two channels' real samples
+ * packed as one complex sequence, 8 channels per workgroup; its error is
+ * that of FP32 transforms, O(2^-24 log2 2048 |h| |x|), not bit-reproducible
+ * across chunkings).  Both methods keep the same state (the last n_taps - 1
+ * input rows), so a stream may switch between calls.  Selecting FFT builds
+ * its tables (taps' spectrum in FP64, rounded; synchronous).  Calls with
+ * more than 65535 blocks are refused.
+ */
+#define FILARK_FIR_DIRECT 0
+#define FILARK_FIR_FFT 1
+filark_status filark_fir_set_method(filark_fir_t st, int method, hipStream_t stream);
 filark_status filark_fir_set_tile(filark_fir_t st, int rows, int waves, int order);
 filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
                                  hipStream_t stream);

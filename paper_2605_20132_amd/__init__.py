@@ -36,7 +36,7 @@ EXPORTS = (
     "filark_batch_launch", "filark_batch_capture", "filark_autotune", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
     "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
     "filark_sos_filtfilt", "filark_sos_filtfilt_noalloc", "filark_ema_init", "filark_ema_process", "filark_ema_state_get", "filark_ema_state_set",
-    "filark_ema_destroy", "filark_fir_init", "filark_fir_set_tile", "filark_fir_process", "filark_fir_state_get",
+    "filark_ema_destroy", "filark_fir_init", "filark_fir_set_tile", "filark_fir_set_method", "filark_fir_process", "filark_fir_state_get",
     "filark_fir_state_set", "filark_fir_destroy",
 )
 
@@ -103,6 +103,7 @@ def lib():
     L.filark_ema_destroy.argtypes = [vp]
     L.filark_fir_init.argtypes = [ctypes.POINTER(vp), D, ctypes.c_int, i64, vp]
     L.filark_fir_set_tile.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    L.filark_fir_set_method.argtypes = [vp, ctypes.c_int, vp]
     L.filark_fir_process.argtypes = [vp, vp, vp, i64, i64, vp]
     L.filark_fir_state_get.argtypes = [vp, vp, vp]
     L.filark_fir_state_set.argtypes = [vp, vp, vp]
@@ -575,6 +576,12 @@ class Fir:
 
     def set_tile(self, rows: int, waves: int, order: int = 2):
         _check(lib().filark_fir_set_tile(self._h, int(rows), int(waves), int(order)))
+
+    def set_method(self, method: str, stream=None):
+        """'direct' (default) or 'fft' (FFT filtering in 2048-row windows,
+        up to 1024 taps); the carried history is shared by both."""
+        m = {"direct": 0, "fft": 1}[method]
+        _check(lib().filark_fir_set_method(self._h, m, _stream(stream)))
 
     def process(self, x, out=None, stream=None):
         import torch

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libfilark.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["fwd_l48.hip", "fwd_l64.hip", "fwd_l32.hip", "fwd.hip", "adj.hip", "api.cpp", "design.cpp", "trig.hip",
-           "ema.hip", "fir.hip"]
+           "ema.hip", "fir.hip", "fft.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

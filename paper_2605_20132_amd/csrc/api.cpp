@@ -262,6 +262,8 @@ struct filark_fir_state {
   uint32_t *d_ctl = nullptr;      // [2]: [0] & 1 names the current history buffer
   int rows = 0, waves = 1;        // output rows per wave (0: by launch), waves per workgroup
   int order = 2;                  // workgroup order: a channel slab per XCD, swept row block by row block
+  int method = FILARK_FIR_DIRECT;
+  float2 *d_fft = nullptr;        // FFT method: twiddles [2048], then the taps' spectrum [1025]
 };
 
 struct filark_trigger_state {
@@ -1710,6 +1712,53 @@ filark_status filark_fir_set_tile(filark_fir_t st, int rows, int waves, int orde
   return FILARK_OK;
 }
 
+filark_status filark_fir_set_method(filark_fir_t st, int method, hipStream_t stream) {
+  if (!st) return fail(FILARK_EINVAL, "null state");
+  if (method != FILARK_FIR_DIRECT && method != FILARK_FIR_FFT) return fail(FILARK_EINVAL, "unknown method %d", method);
+  if (method == FILARK_FIR_FFT && !st->d_fft) {
+    // twiddles W_1024^j and W_2048^k, and H[k] = sum_n h[n] W_2048^(n k) / 4096
+    // (the FP32 taps the direct kernel uses, summed in FP64; 1 / 4096 folds
+    // the inverse's 1 / 1024 and the real-transform halves)
+    constexpr int N = kFftN, N2 = kFftN / 2;
+    std::vector<float2> tab((size_t)N + N2 + 1);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int j = 0; j < N2; ++j) {
+      const double a = -two_pi * j / N2;
+      tab[j] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    for (int k = 0; k < N2; ++k) {
+      const double a = -two_pi * k / N;
+      tab[N2 + k] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    const int prev_dev = current_device();
+    if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));
+    std::vector<double> h(st->n_taps);
+    std::vector<float> hf((size_t)st->n_pad);
+    hipError_t e = hipMemcpy(hf.data(), st->d_h, hf.size() * sizeof(float), hipMemcpyDeviceToHost);
+    for (int n = 0; n < st->n_taps; ++n) h[n] = (double)hf[n];
+    for (int k = 0; k <= N2; ++k) {
+      double re = 0.0, im = 0.0;
+      for (int n = 0; n < st->n_taps; ++n) {
+        const double a = -two_pi * (double)(((int64_t)n * k) % N) / N;
+        re += h[n] * std::cos(a);
+        im += h[n] * std::sin(a);
+      }
+      tab[N + k] = make_float2((float)(re / 4096.0), (float)(im / 4096.0));
+    }
+    if (e == hipSuccess) e = hipMalloc(&st->d_fft, tab.size() * sizeof(float2));
+    if (e == hipSuccess) e = hipMemcpy(st->d_fft, tab.data(), tab.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess && st->d_fft) {
+      (void)hipFree(st->d_fft);
+      st->d_fft = nullptr;
+    }
+    if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
+    if (e != hipSuccess) return fail(FILARK_EHIP, "FFT tables: %s", hipGetErrorString(e));
+  }
+  (void)stream;
+  st->method = method;
+  return FILARK_OK;
+}
+
 filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, int64_t n_ch, int64_t n_t,
                                  hipStream_t stream) {
   if (!st) return fail(FILARK_EINVAL, "null state");
@@ -1720,6 +1769,29 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
   {
     const uintptr_t a = (uintptr_t)in, b = (uintptr_t)out, n = (uintptr_t)(n_t * n_ch * 4);
     if (a < b + n && b < a + n) return fail(FILARK_EINVAL, "FIR input and output must not overlap");
+  }
+  if (st->method == FILARK_FIR_FFT) {
+    FftParams q;
+    std::memset(&q, 0, sizeof q);
+    q.x = in;
+    q.y = out;
+    q.tw = st->d_fft;
+    q.H = st->d_fft + kFftN;
+    q.hist0 = st->d_hist[0];
+    q.hist1 = st->d_hist[1];
+    q.ctl = st->d_ctl;
+    q.n_ch = n_ch;
+    q.n_t = n_t;
+    q.hm = st->n_taps - 1;
+    q.B = kFftN - q.hm;
+    if ((n_t + q.B - 1) / q.B > 65535) return fail(FILARK_EINVAL, "n_t too large for one FFT call");
+    const int prev_dev = current_device();
+    if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));
+    hipError_t e = launch_fir_fft(q, stream);
+    if (e == hipSuccess) e = launch_fir_flip(st->d_ctl, stream);
+    if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
+    if (e != hipSuccess) return fail(FILARK_EHIP, "FFT launch failed: %s", hipGetErrorString(e));
+    return FILARK_OK;
   }
   const int64_t W = fir_window_rows(st);
   if (W < 1) return fail(FILARK_EINVAL, "n_ch too large for this FIR tile");
@@ -1800,6 +1872,7 @@ filark_status filark_fir_state_set(filark_fir_t st, const float *hist, hipStream
 
 filark_status filark_fir_destroy(filark_fir_t st) {
   if (!st) return FILARK_OK;
+  if (st->d_fft) (void)hipFree(st->d_fft);
   if (st->d_h) (void)hipFree(st->d_h);
   for (int i = 0; i < 2; ++i)
     if (st->d_hist[i]) (void)hipFree(st->d_hist[i]);

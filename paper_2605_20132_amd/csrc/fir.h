@@ -42,6 +42,23 @@ inline bool fir_rows_ok(int R) { return R == 16 || R == 32 || R == 48; }
 
 hipError_t launch_fir(const FirParams &p, int R, hipStream_t stream);
 
+// FFT filtering (fft.hip): blocks of B = kFftN - (M - 1) output rows, each
+// from a window of kFftN input rows (overlap-save); then the new history is
+// written to the buffer ctl[0] does not name.  M <= 1024.
+constexpr int kFftN = 2048;
+struct FftParams {
+  const float *x;         // chunk [n_t][n_ch]
+  float *y;               // output [n_t][n_ch]
+  const float2 *tw;       // [1024] W_1024^j, then [1024] W_2048^k (FP32 of FP64 values)
+  const float2 *H;        // [1025] the taps' 2048-point spectrum, scaled by 1 / 4096
+  float *hist0, *hist1;   // history buffers [M - 1][n_ch] (as FirParams)
+  const uint32_t *ctl;
+  int64_t n_ch, n_t;
+  int32_t hm;             // M - 1
+  int32_t B;              // output rows per block
+};
+hipError_t launch_fir_fft(const FftParams &p, hipStream_t stream);
+
 // Ends a call: the history buffer its launches wrote becomes the current one
 // (a one-lane kernel, so that graph replays alternate the buffers too).
 hipError_t launch_fir_flip(uint32_t *ctl, hipStream_t stream);

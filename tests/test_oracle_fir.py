@@ -50,3 +50,22 @@ def test_chunked_equals_one_shot_and_history(splits):
         t += n
     np.testing.assert_array_equal(np.concatenate(parts), one)
     np.testing.assert_array_equal(f.hist, x[-(M - 1):])
+
+
+@pytest.mark.parametrize("M,splits", [(1, [3000]), (64, [1, 1000, 1999]), (256, [255, 0, 2745]), (1024, [1023, 1977])])
+def test_matches_overlap_add_convolution(M, splits):
+    """FFT filtering (Table 1's overlap-add row) computes the same linear
+    convolution: scipy's oaconvolve of the whole record, cut at the record's
+    length, equals the oracle fed chunk by chunk (the history carried), within
+    FP64 transform rounding."""
+    rng = np.random.default_rng(M)
+    h = rng.standard_normal(M)
+    x = rng.standard_normal((sum(splits), 3))
+    ref = signal.oaconvolve(x, h[:, None], axes=0)[:x.shape[0]]
+    f, parts, t = oracle.Fir(h, 3), [], 0
+    for n in splits:
+        parts.append(f.process(x[t:t + n]))
+        t += n
+    got = np.concatenate(parts)
+    scale = np.sqrt(M) * np.max(np.abs(x))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12 * scale)
