@@ -29,7 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "channel-samples/s and % HBM peak, plain fwd vs batched vs fwd+adjoint at ≤1e-5 rel err"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2605_20132_amd", "csrc", f) for f in ("fwd.hip", "device.h", "internal.h")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2605_20132_amd", "csrc", f)
+               for f in ("fwd_body.h", "fwd_l48.hip", "device.h", "internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel_6000ch_traffic.json")
 
 
@@ -78,10 +79,24 @@ def copy_bandwidth(torch, dev, mib: int = 512, reps: int = 10) -> float:
     return 2.0 * n * 4 / (ms / 1e3) / 1e9
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_dev, sos, nsta, nlta, chunk, min_seconds=10.0, max_passes=30):
     """Time the FP64 oracle (as it is) on the same record: whole passes over
     all channels in the workload's chunks, state carried, repeated until at
-    least `min_seconds` of wall time (bounded by `max_passes`)."""
+    least `min_seconds` of wall time (bounded by `max_passes`).  Beside it:
+    the same on one host thread over a slice of the channels, and the
+    oracle's forward + adjoint (the gradient of the differentiation workload's
+    loss) over a slice, both scaled to channel-samples/s."""
     import oracle
 
     cores = len(os.sched_getaffinity(0))
@@ -98,10 +113,34 @@ def cpu_baseline(x_dev, sos, nsta, nlta, chunk, min_seconds=10.0, max_passes=30)
         el = time.perf_counter() - t0
         if el >= min_seconds or passes >= max_passes:
             break
-    return {"value": passes * n_ch * n_t / el, "unit": "channel-samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"{passes} pass(es) over the whole record ({n_ch} channels x {n_t} samples in "
-                      f"{(n_t + chunk - 1) // chunk} chunks, state carried), FP64 DF2T cascade + STA/LTA, "
-                      f"{el:.1f} s on {cores} host threads"}
+    res = {"value": passes * n_ch * n_t / el, "unit": "channel-samples/s", "cores": cores, "kind": "oracle",
+           "cpu_model": cpu_model(),
+           "sample": f"{passes} pass(es) over the whole record ({n_ch} channels x {n_t} samples in "
+                     f"{(n_t + chunk - 1) // chunk} chunks, state carried), FP64 DF2T cascade + STA/LTA, "
+                     f"{el:.1f} s on {cores} host threads"}
+    # one thread, the first 1024 channels of the record
+    oracle.set_num_threads(1)
+    sub = np.ascontiguousarray(xs[:, :1024])
+    s1 = oracle.Stream(sos, sub.shape[1], nsta, nlta)
+    t0 = time.perf_counter()
+    for c0 in range(0, n_t, chunk):
+        s1.process(sub[c0:c0 + chunk])
+    el1 = time.perf_counter() - t0
+    res["single_thread"] = {"value": sub.size / el1, "unit": "channel-samples/s", "cores": 1,
+                            "sample": f"{sub.shape[1]} channels x {n_t} samples in chunks of {chunk}, {el1:.1f} s"}
+    # forward + adjoint: the oracle's reverse-mode gradient of mean (cf - target)^2
+    # over 30,000 samples of 2048 channels, on every host thread
+    oracle.set_num_threads(cores)
+    n_g = min(n_t, 30_000)
+    xg = np.ascontiguousarray(xs[:n_g, :2048])
+    tg = np.ascontiguousarray(xg[::-1])
+    t0 = time.perf_counter()
+    oracle.stalta_grad(sos, xg, tg, nsta, nlta, 1.0 / xg.size)
+    elg = time.perf_counter() - t0
+    res["fwd_adjoint"] = {"value": xg.size / elg, "unit": "channel-samples/s", "cores": cores,
+                          "sample": f"{xg.shape[1]} channels x {n_g} samples, one chunk, gradient wrt x and "
+                                    f"all coefficients, {elg:.1f} s"}
+    return res
 
 
 def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
@@ -127,6 +166,7 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
         F.sos_stalta_process(st_t, sl_t, x[a:b], cf=tgt[a:b], write_y=False)
     st, sl = F.SOSState(sos, n_ch), F.StaLtaState(float(nsta), float(nlta), 1.0, n_ch)
     cks = [(st.save(), sl.save()) for _ in splits]
+    tapes = [torch.empty(F.adjoint_tape_bytes(st, sl, b - a), dtype=torch.uint8, device=dev) for a, b in splits]
     zero_z, zero_s = st.save(), sl.save()
     cf = torch.empty_like(x)
     gx = torch.empty_like(x)
@@ -134,7 +174,24 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
     gs = torch.zeros((K, 5), dtype=torch.float64, device=dev)
     scale = 1.0 / x.numel()
 
-    def step():
+    def step(mid=None):
+        # the forward records each chunk's tape; the adjoint reads it
+        st.load(zero_z)
+        sl.load(zero_s)
+        for i, (a, b) in enumerate(splits):
+            F.sos_stalta_process_tape(st, sl, x[a:b], tape=tapes[i], cf=cf[a:b])
+        if mid is not None:
+            mid.record()
+        adj.zero_()
+        gs.zero_()
+        for i in reversed(range(len(splits))):
+            a, b = splits[i]
+            F.sos_stalta_adjoint_tape(st, sl, tapes[i], x[a:b], tgt[a:b], gx[a:b], adj, gs, mode="mse",
+                                      scale=scale)
+
+    def step_checkpoints():
+        # the same without tapes: state checkpoints per chunk, and the
+        # adjoint reruns a states-only forward over each chunk
         st.load(zero_z)
         sl.load(zero_s)
         for i, (a, b) in enumerate(splits):
@@ -151,19 +208,45 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
 
     step()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        step()
-    e1.record()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    mids = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev[0].record()
+    for i in range(steps):
+        step(mids[i])
+        ev[i + 1].record()
     torch.cuda.synchronize()
     st.check()
-    ms = e0.elapsed_time(e1) / steps
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    ms_f = sum(ev[i].elapsed_time(mids[i]) for i in range(steps)) / steps
+    ms_a = sum(mids[i].elapsed_time(ev[i + 1]) for i in range(steps)) / steps
+    step_checkpoints()
+    torch.cuda.synchronize()
+    ev[0].record()
+    step_checkpoints()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_ck = ev[0].elapsed_time(ev[1])
+    n = n_ch * n_t
+    gbs = 20.0 * n / (ms / 1e3) / 1e9
     res = {"workload": f"{n_ch} ch x {n_t} samples @ {w.fs:g} Hz in {len(splits)} chunks of {chunk}; "
                        f"BP order {w.order} ({K} SOS) + STA/LTA {nsta}/{nlta}; loss mean (cf - target)^2; "
                        "grad wrt x and all coefficients",
-           "ms_per_step": ms, "value": n_ch * n_t / (ms / 1e3), "unit": "channel-samples/s",
-           "algorithmic_gbs": 20.0 * n_ch * n_t / (ms / 1e3) / 1e9}
+           "ms_per_step": ms, "value": n / (ms / 1e3), "unit": "channel-samples/s", "algorithmic_gbs": gbs,
+           # algorithmic bytes: forward x read + cf written (8 B per channel-sample),
+           # adjoint x and target read + dL/dx written (12 B); checkpoints and
+           # carried states are under 0.1 % of it
+           "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "whole step: fwd_kernel<K=4, 64-row blocks, stalta> per chunk writing the tape, "
+                                  "then per chunk (last first) adj_kernel per 512-row window",
+                        "algorithmic_bytes_per_step": 20.0 * n,
+                        "forward": {"ms": ms_f, "algorithmic_gbs": 8.0 * n / (ms_f / 1e3) / 1e9,
+                                    "frac": 8.0 * n / (ms_f / 1e3) / 1e9 / HBM_PEAK_GBS},
+                        "adjoint": {"ms": ms_a, "algorithmic_gbs": 12.0 * n / (ms_a / 1e3) / 1e9,
+                                    "frac": 12.0 * n / (ms_a / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                    "kernel": "adj_kernel<4, 16, unit, rebuild> (60 launches per step) and "
+                                              "adj_reduce_kernel (10)"}},
+           "checkpoint_path_ms_per_step": ms_ck}
     if parity:
         # the same path on a 64-channel slice against the oracle's reference gradient
         import numpy as np
@@ -173,19 +256,14 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
         ts = tgt[:, :64].contiguous()
         osos = oracle.butter_sos(w.order, w.btype, w.f1, w.f2, w.fs)
         s2, l2 = F.SOSState(osos, 64), F.StaLtaState(float(nsta), float(nlta), 1.0, 64)
-        ck2 = []
-        for a, b in splits:
-            ck2.append((s2.save(), l2.save()))
-            F.sos_stalta_process(s2, l2, xs[a:b], write_y=False)
+        tp2 = [F.sos_stalta_process_tape(s2, l2, xs[a:b])[2] for a, b in splits]
         g2 = torch.empty_like(xs)
         a2 = torch.zeros((2 * K + 2, 64), dtype=torch.float64, device=dev)
         gs2 = torch.zeros((K, 5), dtype=torch.float64, device=dev)
         sc2 = 1.0 / xs.numel()
         for i in reversed(range(len(splits))):
             a, b = splits[i]
-            s2.load(ck2[i][0])
-            l2.load(ck2[i][1])
-            F.sos_stalta_adjoint(s2, l2, xs[a:b], ts[a:b], g2[a:b], a2, gs2, mode="mse", scale=sc2)
+            F.sos_stalta_adjoint_tape(s2, l2, tp2[i], xs[a:b], ts[a:b], g2[a:b], a2, gs2, mode="mse", scale=sc2)
         torch.cuda.synchronize()
         _, ogx, ogs, _ = oracle.stalta_grad(osos, xs.double().cpu().numpy(), ts.double().cpu().numpy(), nsta,
                                             nlta, sc2)
@@ -196,7 +274,8 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
                          "max_rel_rms_gx": float(np.max(num / np.where(den > 0, den, 1.0))),
                          "rel_l2_gtheta": float(np.linalg.norm(gs2.cpu().numpy() - ogs) / np.linalg.norm(ogs)),
                          "tolerance": 1e-5}
-    log(f"[bench] fwd+adjoint {ms:.2f} ms/step -> {res['value']:.3e} ch-samples/s"
+    log(f"[bench] fwd+adjoint {ms:.2f} ms/step (forward {ms_f:.2f}, adjoint {ms_a:.2f}; checkpoint path "
+        f"{ms_ck:.2f}) -> {res['value']:.3e} ch-samples/s"
         + (f"; parity gx {res['parity']['max_rel_rms_gx']:.2e} gtheta {res['parity']['rel_l2_gtheta']:.2e}"
            if parity else ""))
     return res
@@ -642,19 +721,6 @@ def extras(args, torch, dev, F, st, sl, step, x, y, cf, chunk, n_chunks, n_t, n_
     except Exception as e:  # capture is an optional extra measurement
         log(f"[bench] graph capture unavailable: {e}")
 
-    if args.calib_copy:
-        src = torch.empty(128 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        flush = torch.empty(256 << 20, dtype=torch.float32, device=dev)
-        flush.fill_(2.0)  # 1 GiB written after src: src is not cache resident when copied
-        del flush
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
-        del src, dst
-
     copy_gbs = copy_bandwidth(torch, dev)
     log(f"[bench] on-box device copy {copy_gbs:.0f} GB/s (read + write)")
     return pair_ms, graph, copy_gbs
@@ -782,6 +848,19 @@ def main():
     achieved = bytes_launch / (kern_ms / 1e3) / 1e9
     log(f"[bench] kernel avg {kern_ms * 1e3:.1f} us/launch over the timed region -> {achieved:.0f} GB/s algorithmic")
 
+    if args.calib_copy:
+        src = torch.empty(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        flush = torch.empty(256 << 20, dtype=torch.float32, device=dev)
+        flush.fill_(2.0)  # 1 GiB written after src: src is not cache resident when copied
+        del flush
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {src.numel() * 4} bytes done")
+        del src, dst
+
     pair_ms, graph, copy_gbs = None, None, None
     if not args.profile:
         pair_ms, graph, copy_gbs = extras(args, torch, dev, F, st, sl, step, x, y, cf, chunk, n_chunks, n_t, n_ch,
@@ -789,7 +868,7 @@ def main():
 
     batched = None
     if not args.no_batched:
-        batched = batched_leg(F, torch, dev, 200, not args.no_parity)
+        batched = batched_leg(F, torch, dev, 40 if args.profile else 200, not args.no_parity)
 
     trig = None
     if not args.no_trigger:

@@ -277,6 +277,38 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
                                         double *gsos, int64_t n_ch, int64_t n_t, hipStream_t stream);
 
 /*
+ * The adjoint with a tape: the forward call records what the adjoint needs,
+ * so the adjoint runs no forward pass of its own and reads no object state.
+ *   _tape_bytes  size of the tape of one chunk of n_t rows: the forward
+ *                state at the start of every adjoint window of the chunk
+ *                (windows of the adjoint tile's rows, 512 by default), each
+ *                slot the filter state [2K][n_ch], (sta, lta) [2][n_ch] and
+ *                the sample counter [n_ch] (FP64 / int64).  Fails with
+ *                FILARK_EINVAL when the adjoint window is not a multiple of
+ *                64 rows that divides 2048 (the default adjoint tile is).
+ *   _process_tape  filark_sos_stalta_process (cf required, y optional), run
+ *                with 64-row blocks, that also writes the chunk's tape into
+ *                `tape` (device, caller-owned, _tape_bytes bytes for this
+ *                n_t).  The objects' state advances as in the plain call; cf
+ *                and the state agree with it to rounding (a different block
+ *                length sums in a different order).  Asynchronous on `stream`.
+ *   _adjoint_tape  filark_sos_stalta_adjoint over the same chunk from its
+ *                tape (arguments as there); the objects only supply the
+ *                filter, the windows and the tiles, and their state is
+ *                neither read nor written, so no checkpoint needs restoring.
+ *                The adjoint tile must be the one the tape was written with.
+ * Errors: FILARK_EINVAL, FILARK_ESHAPE, FILARK_EHIP.
+ */
+filark_status filark_adjoint_tape_bytes(filark_sos_t sos, filark_stalta_t sl, int64_t n_t, size_t *bytes);
+filark_status filark_sos_stalta_process_tape(filark_sos_t sos, filark_stalta_t sl, const float *x, float *y,
+                                             float *cf, void *tape, int64_t n_ch, int64_t n_t,
+                                             hipStream_t stream);
+filark_status filark_sos_stalta_adjoint_tape(filark_sos_t sos, filark_stalta_t sl, const void *tape,
+                                             const float *x, const float *g, int mode, double scale, float *gx,
+                                             double *adj, double *gsos, int64_t n_ch, int64_t n_t,
+                                             hipStream_t stream);
+
+/*
  * Batched filtering of many independent streams in one launch (the stateful
  * SOS operator of Section 3.4 applied to several records at once; streams
  * may differ in channel count, chunk length and filter).

@@ -32,7 +32,8 @@ EXPORTS = (
     "filark_stalta_process", "filark_sos_stalta_process", "filark_state_get", "filark_state_set",
     "filark_check", "filark_sos_destroy", "filark_stalta_destroy", "filark_last_error",
     "filark_version", "filark_tile_set", "filark_tile_get", "filark_state_bytes", "filark_state_save",
-    "filark_state_load", "filark_sos_stalta_adjoint", "filark_batch_create", "filark_batch_bind",
+    "filark_state_load", "filark_sos_stalta_adjoint", "filark_adjoint_tape_bytes",
+    "filark_sos_stalta_process_tape", "filark_sos_stalta_adjoint_tape", "filark_batch_create", "filark_batch_bind",
     "filark_batch_launch", "filark_batch_capture", "filark_autotune", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
     "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
     "filark_sos_filtfilt", "filark_sos_filtfilt_noalloc", "filark_ema_init", "filark_ema_process", "filark_ema_state_get", "filark_ema_state_set",
@@ -81,6 +82,10 @@ def lib():
     L.filark_state_load.argtypes = [vp, ctypes.c_int, vp, vp]
     L.filark_sos_stalta_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp, i64,
                                             i64, vp]
+    L.filark_adjoint_tape_bytes.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.filark_sos_stalta_process_tape.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp]
+    L.filark_sos_stalta_adjoint_tape.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp,
+                                                 i64, i64, vp]
     L.filark_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), vp]
     L.filark_batch_bind.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64), vp]
     L.filark_batch_launch.argtypes = [vp, vp]
@@ -393,6 +398,64 @@ def sos_stalta_adjoint(sos: SOSState, sl: StaLtaState, x, g, gx=None, adj=None, 
     _check(lib().filark_sos_stalta_adjoint(sos.handle, sl.handle, _dev_f32(x, "x"), _dev_f32(g, "g"), m,
                                            float(scale), _dev_f32(gx, "gx"), ctypes.c_void_p(adj.data_ptr()),
                                            ctypes.c_void_p(gsos.data_ptr()), n_ch, n_t, _stream(stream)))
+    return gx, adj, gsos
+
+
+def adjoint_tape_bytes(sos: SOSState, sl: StaLtaState, n_t: int) -> int:
+    """Bytes of the adjoint tape of one chunk of n_t rows."""
+    n = ctypes.c_size_t()
+    _check(lib().filark_adjoint_tape_bytes(sos.handle, sl.handle, int(n_t), ctypes.byref(n)))
+    return int(n.value)
+
+
+def sos_stalta_process_tape(sos: SOSState, sl: StaLtaState, x, tape=None, y=None, cf=None, stream=None):
+    """The fused forward over one chunk that also records the chunk's adjoint
+    tape (the forward state at every adjoint window start).  tape: a uint8
+    CUDA tensor of adjoint_tape_bytes bytes (allocated if None).  Returns
+    (y or None, cf, tape)."""
+    import torch
+
+    n_t, n_ch = x.shape
+    if cf is None:
+        cf = torch.empty_like(x)
+    if tape is None:
+        tape = torch.empty(adjoint_tape_bytes(sos, sl, n_t), dtype=torch.uint8, device=x.device)
+    if not tape.is_cuda or not tape.is_contiguous() or tape.numel() * tape.element_size() < adjoint_tape_bytes(
+            sos, sl, n_t):
+        raise FilarkError(EINVAL, "tape must be a contiguous CUDA tensor of adjoint_tape_bytes bytes")
+    _check(lib().filark_sos_stalta_process_tape(sos.handle, sl.handle, _dev_f32(x, "x"),
+                                                _dev_f32(y, "y") if y is not None else None, _dev_f32(cf, "cf"),
+                                                ctypes.c_void_p(tape.data_ptr()), n_ch, n_t, _stream(stream)))
+    return y, cf, tape
+
+
+def sos_stalta_adjoint_tape(sos: SOSState, sl: StaLtaState, tape, x, g, gx=None, adj=None, gsos=None,
+                            mode: str = "grad", scale: float = 1.0, stream=None):
+    """sos_stalta_adjoint from the chunk's tape (the objects' state is not
+    used).  Returns (gx, adj, gsos)."""
+    import torch
+
+    n_t, n_ch = x.shape
+    K = sos.n_sec
+    if gx is None:
+        gx = torch.empty_like(x)
+    if adj is None:
+        adj = torch.zeros((2 * K + 2, n_ch), dtype=torch.float64, device=x.device)
+    if gsos is None:
+        gsos = torch.zeros((K, 5), dtype=torch.float64, device=x.device)
+    for t, name in ((adj, "adj"), (gsos, "gsos")):
+        if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+            raise FilarkError(EINVAL, f"{name} must be a contiguous float64 CUDA tensor")
+    if adj.shape != (2 * K + 2, n_ch) or gsos.shape != (K, 5):
+        raise FilarkError(EINVAL, "adj must be [2K+2, n_ch] and gsos [K, 5]")
+    if not tape.is_cuda or not tape.is_contiguous() or tape.numel() * tape.element_size() < adjoint_tape_bytes(
+            sos, sl, n_t):
+        raise FilarkError(EINVAL, "tape must be a contiguous CUDA tensor of adjoint_tape_bytes bytes")
+    m = {"grad": ADJ_GRAD, "mse": ADJ_MSE}[mode]
+    _check(lib().filark_sos_stalta_adjoint_tape(sos.handle, sl.handle, ctypes.c_void_p(tape.data_ptr()),
+                                                _dev_f32(x, "x"), _dev_f32(g, "g"), m, float(scale),
+                                                _dev_f32(gx, "gx"), ctypes.c_void_p(adj.data_ptr()),
+                                                ctypes.c_void_p(gsos.data_ptr()), n_ch, n_t, _stream(stream)))
     return gx, adj, gsos
 
 

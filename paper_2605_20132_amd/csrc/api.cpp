@@ -306,9 +306,10 @@ Tile checkpoint_tile() {
 
 // Checkpoint emission of a forward launch (FwdParams::ck).
 struct CkSpec {
-  double *base;     // slot of the first checkpoint after the launch start
+  double *base;     // slot of the checkpoint at the first launch's start
   int64_t stride;   // doubles per slot
   int rows;         // rows between checkpoints (a multiple of the block)
+  bool first;       // also write the checkpoint at each launch's start
 };
 
 filark_status upload(double **dst, const std::vector<double> &tab, hipStream_t stream) {
@@ -452,6 +453,7 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
       p.ck = ck->base + (t0 / ck->rows) * ck->stride;
       p.ck_stride = ck->stride;
       p.ck_blocks = ck->rows / t.block;
+      p.ck_first = ck->first ? 1 : 0;
     }
     e = launch_fwd(p, K, t.block, sl != nullptr, !states_only && (sl == nullptr || y != nullptr),
                    sos != nullptr && sos->cas.unit_tail(), rev, stream);
@@ -932,9 +934,36 @@ filark_status filark_state_load(void *obj, int kind, const void *dev_src, hipStr
   return fail(FILARK_EINVAL, "unknown state kind %d", kind);
 }
 
-filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, const float *x,
-                                        const float *g, int mode, double scale, float *gx, double *adj,
-                                        double *gsos, int64_t n_ch, int64_t n_t, hipStream_t stream) {
+namespace {
+
+// Rows of an adjoint window and doubles of one checkpoint slot (filter state
+// [2K][n_ch], STA/LTA state [2][n_ch], counter [n_ch] in a double slot).
+int64_t adjoint_rows(const filark_sos_state *sos, int64_t n_ch) { return launch_rows(sos->adj.tile, n_ch); }
+size_t ck_slot_doubles(const filark_sos_state *sos, int64_t n_ch) {
+  return (size_t)(2 * sos->cas.K + 3) * (size_t)n_ch;
+}
+
+// A tape's forward: the checkpoint tile (64-row blocks, so that every
+// adjoint window start that is a multiple of 64 rows falls on a block start;
+// 4 waves and groups of 8 channels, so that with the 64-row kernel's
+// registers every workgroup of a 6000-channel chunk is resident at once).
+Tile tape_tile(const filark_sos_state *sos, int64_t) { return sos->ckp.tile; }
+
+// Why a tape cannot be used with these objects and this channel count, or null.
+const char *tape_unusable(const filark_sos_state *sos, const filark_stalta_state *sl, int64_t n_ch) {
+  const Tile tt = tape_tile(sos, n_ch);
+  const int64_t rows = adjoint_rows(sos, n_ch);
+  if (!(sl->ckp.tile == sos->ckp.tile)) return "the states' checkpoint tiles differ";
+  if (!(sos->adj.tile == sl->adj.tile)) return "the adjoint tile shapes of the states differ";
+  if (rows == 0 || launch_rows(tt, n_ch) == 0) return "too many channels for the tape's windows";
+  if (rows % tt.block != 0 || tt.window() % rows != 0)
+    return "the adjoint window must be a multiple of 64 rows that divides 2048";
+  return nullptr;
+}
+
+filark_status adjoint_run(filark_sos_t sos, filark_stalta_t sl, const double *tape, const float *x,
+                          const float *g, int mode, double scale, float *gx, double *adj, double *gsos,
+                          int64_t n_ch, int64_t n_t, hipStream_t stream) {
   if (!sos || !sl) return fail(FILARK_EINVAL, "null state");
   if (sos->device != sl->device) return fail(FILARK_EINVAL, "states live on different devices");
   if (sos->n_ch != n_ch || sl->n_ch != n_ch) return fail(FILARK_ESHAPE, "n_ch differs from the states'");
@@ -958,11 +987,13 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
   if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
 
   // workspace: forward state at every window start after the first (filter
-  // [2K][n_ch], STA/LTA [2][n_ch], counter [n_ch]), per-group coefficient sums
+  // [2K][n_ch], STA/LTA [2][n_ch], counter [n_ch]; the tape's slots instead
+  // when there is one), per-group coefficient sums
   const int64_t n_win = (n_t + rows - 1) / rows;
-  const size_t ck_doubles = (size_t)(2 * K + 3) * (size_t)n_ch;  // the counter rides in a double slot
+  const size_t ck_doubles = ck_slot_doubles(sos, n_ch);
   const int n_grp = (int)((n_ch + ta.group - 1) / ta.group);
-  rc = grow(&sos->d_ck, &sos->ck_bytes, (size_t)n_win * ck_doubles * sizeof(double), stream);
+  rc = FILARK_OK;
+  if (!tape) rc = grow(&sos->d_ck, &sos->ck_bytes, (size_t)n_win * ck_doubles * sizeof(double), stream);
   if (rc == FILARK_OK) rc = grow(&sos->d_gpart, &sos->gpart_bytes, (size_t)n_grp * 5 * K * sizeof(double), stream);
   if (rc != FILARK_OK) {
     if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
@@ -996,13 +1027,15 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
                         sl->ckp.tile == tck &&
                         check_lds(fwd_lds_bytes(K, tck.waves, tck.levels(), tck.group), tck, K, sos->device) ==
                             FILARK_OK;
-  if (one_pass) {
+  if (tape) {
+    // the tape holds every window's start state
+  } else if (one_pass) {
     const int64_t r_end = (n_win - 1) * rows;
     for (int64_t t0 = 0; t0 < r_end && e == hipSuccess; t0 += ck_win) {
       const int64_t nt = std::min(ck_win, r_end - t0);
       const int64_t w0 = t0 / rows, w1 = (t0 + nt) / rows;
       e = seed(w1, w0);
-      const CkSpec cks{ck_z(w0 + 1), (int64_t)ck_doubles, (int)rows};
+      const CkSpec cks{ck_z(w0), (int64_t)ck_doubles, (int)rows, false};
       if (e == hipSuccess)
         e = forward_launches(sos, sl, tck, ck_z(w1), ck_s(w1), ck_c(w1), x + (size_t)t0 * n_ch, nullptr, nullptr,
                              true, n_ch, nt, stream, false, &cks, true);
@@ -1050,15 +1083,82 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
     p.gx = gx + off;
     p.n_t = (int32_t)nt;
     p.range = (int32_t)((uint64_t)nt * rowb);
-    p.zs0 = w == 0 ? sos->d_state : ck_z(w);
-    p.sl0 = w == 0 ? sl->d_state : ck_s(w);
-    p.cnt0 = w == 0 ? sl->d_cnt : ck_c(w);
+    if (tape) {
+      const double *slot = tape + (size_t)w * ck_doubles;
+      p.zs0 = slot;
+      p.sl0 = slot + (size_t)(2 * K) * n_ch;
+      p.cnt0 = reinterpret_cast<const int64_t *>(slot + (size_t)(2 * K + 2) * n_ch);
+    } else {
+      p.zs0 = w == 0 ? sos->d_state : ck_z(w);
+      p.sl0 = w == 0 ? sl->d_state : ck_s(w);
+      p.cnt0 = w == 0 ? sl->d_cnt : ck_c(w);
+    }
     e = launch_adj(p, K, ta.block, sos->cas.unit_tail(), stream);
   }
   if (e == hipSuccess) e = launch_adj_reduce(sos->d_gpart, n_grp, 5 * K, gsos, stream);
   if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "adjoint launch failed: %s", hipGetErrorString(e));
   return FILARK_OK;
+}
+
+}  // namespace
+
+filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, const float *x,
+                                        const float *g, int mode, double scale, float *gx, double *adj,
+                                        double *gsos, int64_t n_ch, int64_t n_t, hipStream_t stream) {
+  return adjoint_run(sos, sl, nullptr, x, g, mode, scale, gx, adj, gsos, n_ch, n_t, stream);
+}
+
+filark_status filark_adjoint_tape_bytes(filark_sos_t sos, filark_stalta_t sl, int64_t n_t, size_t *bytes) {
+  if (!sos || !sl || !bytes) return fail(FILARK_EINVAL, "null pointer");
+  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
+  if (sos->n_ch != sl->n_ch) return fail(FILARK_ESHAPE, "the states' channel counts differ");
+  const char *why = tape_unusable(sos, sl, sos->n_ch);
+  if (why) return fail(FILARK_EINVAL, "no tape: %s", why);
+  const int64_t rows = adjoint_rows(sos, sos->n_ch);
+  *bytes = (size_t)((n_t + rows - 1) / rows) * ck_slot_doubles(sos, sos->n_ch) * sizeof(double);
+  return FILARK_OK;
+}
+
+filark_status filark_sos_stalta_process_tape(filark_sos_t sos, filark_stalta_t sl, const float *x, float *y,
+                                             float *cf, void *tape, int64_t n_ch, int64_t n_t,
+                                             hipStream_t stream) {
+  if (!sos || !sl) return fail(FILARK_EINVAL, "null state");
+  if (sos->device != sl->device) return fail(FILARK_EINVAL, "states live on different devices");
+  if (sos->n_ch != n_ch || sl->n_ch != n_ch) return fail(FILARK_ESHAPE, "n_ch differs from the states'");
+  if (n_t < 0) return fail(FILARK_EINVAL, "n_t out of range: %lld", (long long)n_t);
+  if (n_t == 0) return FILARK_OK;
+  if (!x || !cf || !tape) return fail(FILARK_EINVAL, "null pointer");
+  if (y && (const void *)y == (const void *)cf) return fail(FILARK_EINVAL, "y and cf must differ");
+  const char *why = tape_unusable(sos, sl, n_ch);
+  if (why) return fail(FILARK_EINVAL, "no tape: %s", why);
+  const Tile tt = tape_tile(sos, n_ch);
+  const int K = sos->cas.K;
+  filark_status rc = check_lds(fwd_lds_bytes(K, tt.waves, tt.levels(), tt.group), tt, K, sos->device);
+  if (rc != FILARK_OK) return rc;
+  const int prev_dev = current_device();
+  if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
+  const CkSpec ck{static_cast<double *>(tape), (int64_t)ck_slot_doubles(sos, n_ch), (int)adjoint_rows(sos, n_ch),
+                  true};
+  hipError_t e = forward_launches(sos, sl, tt, sos->d_state, sl->d_state, sl->d_cnt, x, y, cf, false, n_ch, n_t,
+                                  stream, false, &ck, true);
+  if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
+  if (e != hipSuccess) return fail(FILARK_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status filark_sos_stalta_adjoint_tape(filark_sos_t sos, filark_stalta_t sl, const void *tape,
+                                             const float *x, const float *g, int mode, double scale, float *gx,
+                                             double *adj, double *gsos, int64_t n_ch, int64_t n_t,
+                                             hipStream_t stream) {
+  if (!sos || !sl) return fail(FILARK_EINVAL, "null state");
+  if (n_t > 0 && !tape) return fail(FILARK_EINVAL, "null tape");
+  if (sos->n_ch == n_ch && sl->n_ch == n_ch) {
+    const char *why = tape_unusable(sos, sl, n_ch);
+    if (why) return fail(FILARK_EINVAL, "no tape: %s", why);
+  }
+  return adjoint_run(sos, sl, static_cast<const double *>(tape), x, g, mode, scale, gx, adj, gsos, n_ch, n_t,
+                     stream);
 }
 
 filark_status filark_batch_create(filark_batch_t *out, int n, const filark_sos_t *states, hipStream_t stream) {

@@ -430,11 +430,11 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
     lds_barrier();  // the capture below reuses the exchange
     {
       // checkpoints of the filter state at every ck_blocks-th block start
-      // after the first (the adjoint's window starts)
+      // (the adjoint's window starts)
       kparams_t q = ps.get();
       const int ckb = q->ck_blocks;
-      if (ckb > 0 && b > 0 && b % ckb == 0 && (int64_t)b * L < (int64_t)q->n_t && cval) {
-        double *ck = q->ck + (int64_t)(b / ckb - 1) * q->ck_stride;
+      if (ckb > 0 && (b > 0 || q->ck_first) && b % ckb == 0 && (int64_t)b * L < (int64_t)q->n_t && cval) {
+        double *ck = q->ck + (int64_t)(b / ckb) * q->ck_stride;
 #pragma unroll
         for (int i = 0; i < NS; ++i) ck[i * n_ch + c] = z[i];
       }
@@ -494,8 +494,8 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
     kparams_t q = ps.get();
     {  // checkpoints of the STA/LTA state and the sample counter (as the filter's above)
       const int ckb = q->ck_blocks;
-      if (ckb > 0 && b > 0 && b % ckb == 0 && (int64_t)b * L < (int64_t)q->n_t && cval) {
-        double *ck = q->ck + (int64_t)(b / ckb - 1) * q->ck_stride + (int64_t)NS * n_ch;
+      if (ckb > 0 && (b > 0 || q->ck_first) && b % ckb == 0 && (int64_t)b * L < (int64_t)q->n_t && cval) {
+        double *ck = q->ck + (int64_t)(b / ckb) * q->ck_stride + (int64_t)NS * n_ch;
         ck[c] = Sin / q->nsta_d;
         ck[n_ch + c] = Lin / q->nlta_d;
         reinterpret_cast<int64_t *>(ck + 2 * n_ch)[c] = g0 + row0;

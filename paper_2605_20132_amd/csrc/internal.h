@@ -32,13 +32,15 @@ struct FwdParams {
   int32_t out_range;   // buffer range of y and cf: `range`, or 0 to write neither (states only)
   int32_t nt;          // 1: y and cf stores carry the non-temporal hint (groups of >= 16 channels)
   int32_t order;       // channel-group order within an XCD (dev::group_of)
-  // state checkpoints (for the adjoint): at the start of every ck_blocks-th
-  // block after the first, the filter state [2K][n_ch], the STA/LTA state
-  // [2][n_ch] and the sample counter [n_ch] (int64 in a double slot) go to
-  // ck + (i - 1) * ck_stride for the i-th such block; ck_blocks = 0: none
+  // state checkpoints (for the adjoint): at the start of block b, for every
+  // b that is a multiple of ck_blocks (b = 0 only if ck_first), the filter
+  // state [2K][n_ch], the STA/LTA state [2][n_ch] and the sample counter
+  // [n_ch] (int64 in a double slot) go to ck + (b / ck_blocks) * ck_stride;
+  // ck_blocks = 0: none
   double *ck;
   int64_t ck_stride;
   int32_t ck_blocks;
+  int32_t ck_first;
 
   // SOS cascade
   double *zs;          // carried state [2K][n_ch], updated in place

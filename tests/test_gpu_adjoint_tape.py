@@ -1,0 +1,141 @@
+"""GPU parity of the adjoint with a tape (the forward records the state at
+every adjoint window start; the adjoint reads it instead of rerunning a
+forward pass or restoring checkpoints).
+
+Bars as for the plain adjoint (gradient tolerance reading: 1e-5 relative):
+dL/dx per-channel relative RMS <= 1e-5 and the coefficient gradient relative
+L2 <= 1e-5 against the oracle's one-shot gradient, the adjoint state handed
+back within 1e-6 of its scale; the forward's cf within 1e-5 (per-channel
+relative RMS) of the oracle's.  Against the plain adjoint path on the same
+data: the tape's forward runs 64-row blocks where the plain forward runs
+48-row blocks, so the chunk states differ by the rounding of the block scan
+(measured 1e-8 of the state's scale for this bandpass, whose 1 Hz poles sit
+close to the unit circle); the end state, the coefficient gradients and the
+adjoint state are held to 1e-6 of their scale and dL/dx to 2e-7 per-channel
+relative RMS: tighter than the oracle bars, which remain the parity bar.
+Shapes: 24 to 4100 channels (ragged channel groups), chunks shorter than one
+adjoint window, of one row, longer than the tape forward's 2048-row launch
+window, and ragged.
+"""
+
+import numpy as np
+import pytest
+
+from tests.helpers import max_rel_rms
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def F():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_20132_amd as F
+
+    F.lib()
+    return F
+
+
+def _orc():
+    import oracle
+
+    return oracle
+
+
+def _run(F, x, tgt, sos, nsta, nlta, splits, scale, tape: bool):
+    n_t, n_ch = x.shape
+    K = sos.shape[0]
+    st = F.SOSState(sos, n_ch)
+    sl = F.StaLtaState(float(nsta), float(nlta), 1.0, n_ch)
+    cf = torch.empty_like(x)
+    saved = []
+    for a, b in splits:
+        if tape:
+            _, _, tp = F.sos_stalta_process_tape(st, sl, x[a:b].contiguous(), cf=cf[a:b])
+            saved.append(tp)
+        else:
+            saved.append((st.save(), sl.save()))
+            F.sos_stalta_process(st, sl, x[a:b].contiguous(), cf=cf[a:b], write_y=False)
+    zend = st.get_state()
+    gx = torch.empty_like(x)
+    adj = torch.zeros((2 * K + 2, n_ch), dtype=torch.float64, device="cuda")
+    gs = torch.zeros((K, 5), dtype=torch.float64, device="cuda")
+    for (a, b), sv in reversed(list(zip(splits, saved))):
+        ga = torch.empty((b - a, n_ch), dtype=torch.float32, device="cuda")
+        if tape:
+            z_before = st.get_state()
+            F.sos_stalta_adjoint_tape(st, sl, sv, x[a:b].contiguous(), tgt[a:b].contiguous(), ga, adj, gs,
+                                      mode="mse", scale=scale)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(st.get_state(), z_before)  # the objects' state is not used
+        else:
+            st.load(sv[0])
+            sl.load(sv[1])
+            F.sos_stalta_adjoint(st, sl, x[a:b].contiguous(), tgt[a:b].contiguous(), ga, adj, gs, mode="mse",
+                                 scale=scale)
+        gx[a:b] = ga
+    torch.cuda.synchronize()
+    st.check()
+    return cf.cpu().numpy(), zend, gx.cpu().numpy(), adj.cpu().numpy().T, gs.cpu().numpy()
+
+
+@pytest.mark.parametrize("n_ch,splits", [
+    (24, [(0, 1000), (1000, 1001), (1001, 2600), (2600, 3100)]),
+    (37, [(0, 300), (300, 2348), (2348, 2350), (2350, 5000)]),
+    (4100, [(0, 2048), (2048, 3000), (3000, 4500)]),
+])
+def test_tape_chain_matches_oracle_and_plain_adjoint(F, n_ch, splits):
+    orc = _orc()
+    nsta, nlta = 30, 300
+    sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
+    n_t = splits[-1][1]
+    g = torch.Generator(device="cuda").manual_seed(n_ch)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    tgt = torch.rand((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32) * 3.0
+    scale = 1.0 / x.numel()
+    cf, zend, gx, adj, gs = _run(F, x, tgt, sos, nsta, nlta, splits, scale, True)
+    _, zend0, gx0, adj0, gs0 = _run(F, x, tgt, sos, nsta, nlta, splits, scale, False)
+    # the oracle on every channel for small cases, else on sampled channels
+    cols = np.arange(n_ch) if n_ch < 100 else np.array([0, 15, 16, 2047, n_ch - 1])
+    xh = x.cpu().numpy().astype(np.float64)[:, cols]
+    th = tgt.cpu().numpy().astype(np.float64)[:, cols]
+    y, zo = orc.sos_filter(sos, xh)
+    ocf, _, _ = orc.stalta(y, nsta, nlta)
+    assert max_rel_rms(cf[:, cols], ocf) <= 1e-5
+    np.testing.assert_allclose(zend[cols], zo, rtol=0, atol=1e-6 * np.max(np.abs(zo)))
+    _, ogx, ogs, oadj = orc.stalta_grad(sos, xh, th, nsta, nlta, scale)
+    assert max_rel_rms(gx[:, cols], ogx) <= 1e-5
+    ea = float(np.max(np.abs(adj[cols] - oadj)) / np.max(np.abs(oadj)))
+    assert ea <= 1e-6
+    if len(cols) == n_ch:
+        assert float(np.linalg.norm(gs - ogs) / np.linalg.norm(ogs)) <= 1e-5
+    # against the plain path on the same data, every channel
+    assert max_rel_rms(gx, gx0) <= 2e-7
+    assert float(np.linalg.norm(gs - gs0) / np.linalg.norm(gs0)) <= 1e-6
+    assert float(np.max(np.abs(adj - adj0)) / np.max(np.abs(adj0))) <= 1e-6
+    np.testing.assert_allclose(zend, zend0, rtol=0, atol=1e-6 * np.max(np.abs(zend0)))
+
+
+def test_tape_bytes_and_errors(F):
+    orc = _orc()
+    sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
+    n_ch = 10
+    st = F.SOSState(sos, n_ch)
+    sl = F.StaLtaState(20.0, 200.0, 1.0, n_ch)
+    slot = (2 * 4 + 3) * n_ch * 8
+    for n_t, n_win in ((1, 1), (512, 1), (513, 2), (3000, 6)):
+        assert F.adjoint_tape_bytes(st, sl, n_t) == n_win * slot
+    x = torch.zeros((100, n_ch), device="cuda")
+    with pytest.raises(F.FilarkError):  # a tape too small
+        F.sos_stalta_process_tape(st, sl, x, tape=torch.empty(10, dtype=torch.uint8, device="cuda"))
+    # 384-row adjoint windows do not divide the tape's 2048-row launch windows
+    st.set_adjoint_tile(16, 3, 8)
+    sl.set_adjoint_tile(16, 3, 8)
+    with pytest.raises(F.FilarkError):
+        F.adjoint_tape_bytes(st, sl, 1000)
+    # 256-row windows do
+    st.set_adjoint_tile(8, 4, 8)
+    sl.set_adjoint_tile(8, 4, 8)
+    assert F.adjoint_tape_bytes(st, sl, 1000) == 4 * slot
