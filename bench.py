@@ -29,32 +29,31 @@ sys.path.insert(0, ROOT)
 
 METRIC = "channel-samples/s and % HBM peak, plain fwd vs batched vs fwd+adjoint at ≤1e-5 rel err"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2605_20132_amd", "csrc", f)
-               for f in ("fwd_body.h", "fwd_l48.hip", "device.h", "internal.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fwd_kernel_6000ch_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "fwd_kernel_6000ch_traffic.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources) -> str:
     h = hashlib.sha256()
-    for path in KERNEL_SRCS:
-        with open(path, "rb") as f:
+    for name in sources:
+        with open(os.path.join(ROOT, "paper_2605_20132_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current source of its kernel (else None)."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_sha256_16") != kernel_hash():
+        if t.get("kernel_sha256_16") != kernel_hash(t["sources"]):
+            return None
+    except (OSError, ValueError, KeyError):
         return None
     return t
 
@@ -141,6 +140,16 @@ def cpu_baseline(x_dev, sos, nsta, nlta, chunk, min_seconds=10.0, max_passes=30)
                           "sample": f"{xg.shape[1]} channels x {n_g} samples, one chunk, gradient wrt x and "
                                     f"all coefficients, {elg:.1f} s"}
     return res
+
+
+def adj_traffic():
+    """adj_kernel's measured HBM bytes per launch against its algorithmic bytes."""
+    t = measured_traffic(os.path.join(PROFILES, "adj_kernel_6000ch_traffic.json"))
+    if t is None:
+        return None
+    return {"hbm_bytes_per_launch": t["hbm_bytes_per_launch"],
+            "algorithmic_bytes_per_launch": t["algorithmic_bytes_per_launch"],
+            "ratio": t["traffic_over_algorithmic"]}
 
 
 def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
@@ -245,7 +254,8 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
                         "adjoint": {"ms": ms_a, "algorithmic_gbs": 12.0 * n / (ms_a / 1e3) / 1e9,
                                     "frac": 12.0 * n / (ms_a / 1e3) / 1e9 / HBM_PEAK_GBS,
                                     "kernel": "adj_kernel<4, 16, unit, rebuild> (60 launches per step) and "
-                                              "adj_reduce_kernel (10)"}},
+                                              "adj_reduce_kernel (10)",
+                                    "adj_kernel_traffic": adj_traffic()}},
            "checkpoint_path_ms_per_step": ms_ck}
     if parity:
         # the same path on a 64-channel slice against the oracle's reference gradient
@@ -659,13 +669,15 @@ def batched_leg(F, torch, dev, replays: int, parity: bool, rotate: int = 4):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / replays
     work = sum(sp.n_ch * sp.n_t for sp in specs)
+    bt = measured_traffic(os.path.join(PROFILES, "fwd_batch_kernel_12streams_traffic.json"))
+    batch_traffic = bt["hbm_bytes_per_launch"] if bt else None
     # x read and y written (FP32), each stream's state read and written (FP64)
     bytes_launch = 8.0 * work + sum(2 * 2 * (sp.order // 2) * sp.n_ch * 8 for sp in specs)
     achieved = bytes_launch / (ms / 1e3) / 1e9
     res.update({"replays": replays, "ms_per_launch": ms, "value": work / (ms / 1e3), "unit": "channel-samples/s",
                 "algorithmic_gbs": achieved,
                 "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                             "frac": achieved / HBM_PEAK_GBS, "traffic": batch_traffic,
                              "kernel": "fwd_batch_kernel<KMAX=5> (persistent; one reset kernel beside it)",
                              "algorithmic_bytes_per_launch": bytes_launch,
                              "working_set_bytes": rotate * bytes_launch},
