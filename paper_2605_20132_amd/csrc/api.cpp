@@ -1884,6 +1884,8 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
     q.n_t = n_t;
     q.hm = st->n_taps - 1;
     q.B = kFftN - q.hm;
+    q.ch = 8;
+    q.threads = 512;
     if ((n_t + q.B - 1) / q.B > 65535) return fail(FILARK_EINVAL, "n_t too large for one FFT call");
     const int prev_dev = current_device();
     if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));

@@ -4,7 +4,7 @@
 // the samples before the call taken from the carried history (the last M - 1
 // input rows, the state the direct kernel carries too).
 //
-// Block.  A workgroup takes 8 consecutive channels and one block of
+// Block.  A workgroup takes 8 (or 4) consecutive channels and one block of
 // B = N - (M - 1) output rows, N = 2048: the window of N input rows that ends
 // with the block (M - 1 rows before it, from the chunk or the history),
 // whose circular convolution with the zero-padded taps equals the linear one
@@ -21,6 +21,8 @@
 // The factors 1/2 and the 1/1024 of the inverse are folded into H on the
 // host.  FP32 throughout (twiddles and H rounded from FP64); the error bound
 // is that of FP32 transforms, not the direct kernel's exact summation order.
+// The workgroups of the call's last block also write the new history (the
+// last M - 1 input rows) into the other history buffer as they load it.
 #include "device.h"
 #include "fir.h"
 
@@ -28,10 +30,7 @@ namespace filark {
 namespace {
 
 constexpr int kN2 = kFftN / 2;           // complex points per channel
-constexpr int kCh = 8;                   // channels per workgroup
-constexpr int kThreads = 256;
-constexpr int kTpc = kThreads / kCh;     // threads per channel
-constexpr int kPitch = kN2;              // LDS float2 per channel (64 KB for the workgroup)
+constexpr int kPitch = kN2;              // LDS float2 per channel (8 KiB)
 
 // LDS place of point i of a channel: the low five bits xor-ed with the next
 // five (a permutation within each run of 32), so the strided accesses of the
@@ -79,11 +78,11 @@ __device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 
   a3 = csub(d02, d13);
 }
 
-// In-place radix-4 transform of 1024 points of one channel held by kTpc
+// In-place radix-4 transform of 1024 points of one channel held by TPC
 // threads: DIT from digit-reversed input to natural output (forward), or DIF
 // from natural input to digit-reversed output (inverse).  Each stage runs
-// 256 butterflies, 8 per thread, separated by workgroup barriers.
-template <bool INV>
+// 256 butterflies, 256 / TPC per thread, separated by workgroup barriers.
+template <bool INV, int kTpc>
 __device__ __forceinline__ void fft1024(float2 *buf, const float2 *__restrict__ w1024, int tc) {
 #pragma unroll
   for (int st = 0; st < 5; ++st) {
@@ -117,41 +116,80 @@ __device__ __forceinline__ void fft1024(float2 *buf, const float2 *__restrict__ 
 }
 
 // Row t of the chunk for channel c: the chunk (0 <= t < n_t), the history
-// (-(M - 1) <= t < 0, oldest row first) or 0 (past the chunk).
-__device__ __forceinline__ float fft_in(const FftParams &p, const float *hist, int64_t t, int64_t c) {
-  if (c >= p.n_ch || t >= p.n_t) return 0.0f;
-  if (t >= 0) return __builtin_nontemporal_load(p.x + t * p.n_ch + c);
-  const int64_t r = t + p.hm;
-  return r >= 0 ? hist[r * p.n_ch + c] : 0.0f;
+// (-(M - 1) <= t < 0, oldest row first) or 0 (past the chunk, or an invalid
+// channel).  Branch-free, so that a thread's loads are all issued before the
+// first is waited for: where there is no sample, a valid address (the
+// twiddle table) is read and the value replaced by 0.
+__device__ __forceinline__ float fft_in(const FftParams &p, const float *hist, int64_t t, int64_t c, bool cval) {
+  const bool in_x = cval && t >= 0 && t < p.n_t;
+  const bool in_h = cval && t < 0 && t + p.hm >= 0;
+  const float *src = in_x ? p.x + t * p.n_ch + c
+                          : (in_h ? hist + (t + p.hm) * p.n_ch + c : reinterpret_cast<const float *>(p.tw));
+  const float v = __builtin_nontemporal_load(src);
+  return (in_x || in_h) ? v : 0.0f;
 }
 
-__global__ void __launch_bounds__(kThreads) fir_fft_kernel(FftParams p) {
+// kCh channels per workgroup of kThreads threads (kThreads / kCh per
+// channel).  Channel groups are dealt to the XCDs in contiguous slabs, so the
+// groups that share a row's cache lines meet in one L2.  The LDS (8 KiB per
+// channel) allows two workgroups of 8 channels per CU; the register bound
+// keeps that many waves resident.
+template <int kCh, int kThreads>
+__global__ void __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(kThreads * 2 / (4 * 64)))) fir_fft_kernel(FftParams p) {
+  constexpr int kTpc = kThreads / kCh;
   __shared__ float2 lds[kCh * kPitch];
+  __shared__ float2 twl[kN2];  // W_1024^j, read by every butterfly
   const int tid = (int)threadIdx.x;
-  const int cg = (int)blockIdx.x, blk = (int)blockIdx.y;
+  const int cg = dev::group_of(p.per_xcd), blk = (int)blockIdx.y;
+  if ((int64_t)cg * kCh >= p.n_ch) return;  // whole workgroup, before any barrier
   const int64_t c0 = (int64_t)cg * kCh;
   const int64_t t_out = (int64_t)blk * p.B;      // first output row of the block
   const int64_t t_win = t_out - p.hm;            // chunk row of window position 0
-  const float *hist = (p.ctl[0] & 1u) ? p.hist1 : p.hist0;
-  const float2 *w1024 = p.tw;
+  const bool odd = (p.ctl[0] & 1u) != 0;
+  const float *hist = odd ? p.hist1 : p.hist0;
+  float *hist_new = odd ? p.hist0 : p.hist1;
   const float2 *w2048 = p.tw + kN2;
+  for (int i = tid; i < kN2; i += kThreads) twl[i] = p.tw[i];
+  // the new history (the last M - 1 rows before the end of the call, from
+  // the chunk or the old history) lies in the last block's window: its
+  // workgroups write it from the values they load
+  const bool last_blk = p.hm > 0 && (int64_t)(blk + 1) * p.B >= p.n_t;
+  const int64_t h0 = p.n_t - p.hm;  // chunk row of the new history's first row
 
   // load: thread (row rr, channel cc); a wave covers 8 rows of 8 channels;
   // window sample r goes to complex n = r / 2 (real part for even r) at the
   // digit-reversed place
   {
+    constexpr int kStep = kThreads / kCh, kIt = kN2 / kStep;
     const int cc = tid & (kCh - 1), rr0 = tid / kCh;
+    const int64_t c = c0 + cc;
+    const bool cval = c < p.n_ch;
     float2 *buf = lds + cc * kPitch;
-    for (int n = rr0; n < kN2; n += kThreads / kCh) {
-      const int64_t t = t_win + 2 * n;
-      const float e = fft_in(p, hist, t, c0 + cc), o = fft_in(p, hist, t + 1, c0 + cc);
-      buf[pad(rev4(n))] = make_float2(e, o);
+    constexpr int kBatch = 8;  // row pairs in flight per thread
+#pragma unroll 1
+    for (int i0 = 0; i0 < kIt; i0 += kBatch) {
+      float2 v[kBatch];
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        const int64_t t = t_win + 2 * (rr0 + (i0 + i) * kStep);
+        v[i] = make_float2(fft_in(p, hist, t, c, cval), fft_in(p, hist, t + 1, c, cval));
+      }
+#pragma unroll
+      for (int i = 0; i < kBatch; ++i) {
+        buf[pad(rev4(rr0 + (i0 + i) * kStep))] = v[i];
+        if (last_blk && cval) {
+          const int64_t t = t_win + 2 * (rr0 + (i0 + i) * kStep);
+          if (t >= h0 && t < p.n_t) hist_new[(t - h0) * p.n_ch + c] = v[i].x;
+          if (t + 1 >= h0 && t + 1 < p.n_t) hist_new[(t + 1 - h0) * p.n_ch + c] = v[i].y;
+        }
+      }
     }
   }
   __syncthreads();
   const int ch = tid / kTpc, tc = tid & (kTpc - 1);
   float2 *buf = lds + ch * kPitch;
-  fft1024<false>(buf, w1024, tc);
+  fft1024<false, kTpc>(buf, twl, tc);
 
   // spectrum: the real transform of the window times H, and the packing for
   // the inverse, pair (k, 1024 - k) at a time (k = 0 with 512 alone and 512
@@ -183,7 +221,7 @@ __global__ void __launch_bounds__(kThreads) fir_fft_kernel(FftParams p) {
     buf[pad(kN2 - k)] = cadd(cadd(ym, conj2(yk)), mul_i<true>(cmul(conj2(wm), csub(ym, conj2(yk)))));
   }
   __syncthreads();
-  fft1024<true>(buf, w1024, tc);
+  fft1024<true, kTpc>(buf, twl, tc);
 
   // store the block's rows: window position r = hm + i, i < B; complex n = r / 2
   // sits at the digit-reversed place after the DIF transform
@@ -201,32 +239,24 @@ __global__ void __launch_bounds__(kThreads) fir_fft_kernel(FftParams p) {
   }
 }
 
-// The new history: row r of the M - 1 rows before the end of the call, from
-// the chunk (chunk row n_t - (M - 1) + r >= 0) or the old history.
-__global__ void __launch_bounds__(256) fir_hist_kernel(FftParams p) {
-  const int64_t n = (int64_t)p.hm * p.n_ch;
-  const float *old = (p.ctl[0] & 1u) ? p.hist1 : p.hist0;
-  float *nw = (p.ctl[0] & 1u) ? p.hist0 : p.hist1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / p.n_ch, c = i - r * p.n_ch;
-    const int64_t t = p.n_t - p.hm + r;
-    nw[i] = t >= 0 ? p.x[t * p.n_ch + c] : old[(t + p.hm) * p.n_ch + c];
-  }
-}
-
 }  // namespace
 
-hipError_t launch_fir_fft(const FftParams &p, hipStream_t stream) {
+hipError_t launch_fir_fft(const FftParams &p_in, hipStream_t stream) {
+  FftParams p = p_in;
   if (p.B < 1 || p.hm < 0 || p.hm >= kFftN) return hipErrorInvalidValue;
+  const int ch = p.ch == 4 ? 4 : 8;
+  const int thr = p.threads == 512 && ch == 8 ? 512 : 256;
   const int64_t n_blk = (p.n_t + p.B - 1) / p.B;
-  const int64_t n_cg = (p.n_ch + kCh - 1) / kCh;
-  if (n_blk > 65535 || n_cg > ((int64_t)1 << 30)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fir_fft_kernel, dim3((unsigned)n_cg, (unsigned)n_blk), dim3(kThreads), 0, stream, p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || p.hm == 0) return e;
-  const int64_t n = (int64_t)p.hm * p.n_ch;
-  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(fir_hist_kernel, dim3(grid), dim3(256), 0, stream, p);
+  const int64_t n_cg = (p.n_ch + ch - 1) / ch;
+  if (n_blk > 65535 || n_cg > ((int64_t)1 << 28)) return hipErrorInvalidValue;
+  p.per_xcd = (int32_t)((n_cg + 7) / 8);
+  const dim3 grid((unsigned)(8 * p.per_xcd), (unsigned)n_blk);
+  if (ch == 4)
+    hipLaunchKernelGGL((fir_fft_kernel<4, 256>), grid, dim3(256), 0, stream, p);
+  else if (thr == 512)
+    hipLaunchKernelGGL((fir_fft_kernel<8, 512>), grid, dim3(512), 0, stream, p);
+  else
+    hipLaunchKernelGGL((fir_fft_kernel<8, 256>), grid, dim3(256), 0, stream, p);
   return hipGetLastError();
 }
 

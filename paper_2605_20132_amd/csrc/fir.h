@@ -56,6 +56,9 @@ struct FftParams {
   int64_t n_ch, n_t;
   int32_t hm;             // M - 1
   int32_t B;              // output rows per block
+  int32_t ch;             // channels per workgroup: 4 or 8
+  int32_t threads;        // threads per workgroup: 256, or 512 with 8 channels
+  int32_t per_xcd;        // channel groups per XCD slab (set by the launcher)
 };
 hipError_t launch_fir_fft(const FftParams &p, hipStream_t stream);
 
