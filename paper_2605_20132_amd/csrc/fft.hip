@@ -11,8 +11,9 @@
 // at the window's last B positions (overlap-save; overlap-add gives the same
 // sums with the tail carried instead of the history).  Per channel:
 //   z[n] = x[2n] + i x[2n + 1]          two real samples per complex value
-//   Z = FFT_1024(z)                      radix-4, in place in LDS (DIT: the
-//                                        input is placed digit-reversed)
+//   Z = FFT_1024(z)                      radix-4 stages (two at a time in
+//                                        registers), in place in LDS (DIT:
+//                                        the input is placed digit-reversed)
 //   X[k] = E + W_2048^k O, E = (Z[k] + Z*[1024 - k]) / 2, O = (Z[k] - Z*[1024 - k]) / 2i
 //   Y[k] = X[k] H[k]                     H: the taps' 2048-point spectrum
 //   Z'[k] = E' + i O', E' = (Y[k] + Y*[1024 - k]) / 2, O' = W_2048^-k (Y[k] - Y*[1024 - k]) / 2
@@ -78,39 +79,114 @@ __device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 
   a3 = csub(d02, d13);
 }
 
-// In-place radix-4 transform of 1024 points of one channel held by TPC
-// threads: DIT from digit-reversed input to natural output (forward), or DIF
-// from natural input to digit-reversed output (inverse).  Each stage runs
-// 256 butterflies, 256 / TPC per thread, separated by workgroup barriers.
+// Two consecutive radix-4 stages, s and s + 1 (spans S = 4^s and 4 S), as
+// one radix-16 step in registers: a thread takes the 16 points
+// g 16 S + j + m S + n 4 S (j < S; m, n < 4), which stage s combines over m
+// and stage s + 1 over n.  Forward (DIT): twiddle W_4S^(j m), 4-point
+// transform over m, then twiddle W_16S^((j + m S) n), transform over n.
+// Inverse (DIF): the same steps in reverse order, transforms first and
+// conjugate twiddles.  64 groups per transform.
+template <bool INV, int s, int kTpc>
+__device__ __forceinline__ void radix16(float2 *buf, const float2 *__restrict__ w1024, int tc) {
+  constexpr int S = 1 << (2 * s);
+  constexpr int step0 = kN2 / (4 * S), step1 = kN2 / (16 * S);
+#pragma unroll
+  for (int u = 0; u < 64 / kTpc; ++u) {
+    const int t = tc + u * kTpc;  // group 0 .. 63
+    const int j = t & (S - 1), g = t >> (2 * s);
+    const int base = g * 16 * S + j;
+    float2 P[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) P[m][n] = buf[pad(base + m * S + n * 4 * S)];
+    if (!INV) {
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+#pragma unroll
+        for (int m = 1; m < 4; ++m) P[m][n] = cmul(P[m][n], tw<false>(w1024, j * m * step0));
+        dft4<false>(P[0][n], P[1][n], P[2][n], P[3][n]);
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int jp = j + m * S;
+#pragma unroll
+        for (int n = 1; n < 4; ++n) P[m][n] = cmul(P[m][n], tw<false>(w1024, jp * n * step1));
+        dft4<false>(P[m][0], P[m][1], P[m][2], P[m][3]);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int jp = j + m * S;
+        dft4<true>(P[m][0], P[m][1], P[m][2], P[m][3]);
+#pragma unroll
+        for (int n = 1; n < 4; ++n) P[m][n] = cmul(P[m][n], tw<true>(w1024, jp * n * step1));
+      }
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        dft4<true>(P[0][n], P[1][n], P[2][n], P[3][n]);
+#pragma unroll
+        for (int m = 1; m < 4; ++m) P[m][n] = cmul(P[m][n], tw<true>(w1024, j * m * step0));
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) buf[pad(base + m * S + n * 4 * S)] = P[m][n];
+  }
+}
+
+// One radix-4 stage of span S = 4^s: 256 butterflies over points
+// g 4 S + j + m S, twiddle W_4S^(j m) before (DIT) or after (DIF) the
+// 4-point transform.
+template <bool INV, int s, int kTpc>
+__device__ __forceinline__ void radix4(float2 *buf, const float2 *__restrict__ w1024, int tc) {
+  constexpr int S = 1 << (2 * s);
+  constexpr int step = kN2 / (4 * S);
+#pragma unroll
+  for (int u = 0; u < 256 / kTpc; ++u) {
+    const int b = tc + u * kTpc;  // butterfly 0 .. 255
+    const int j = b & (S - 1), g = b >> (2 * s);
+    const int base = g * 4 * S + j;
+    float2 a0 = buf[pad(base)], a1 = buf[pad(base + S)], a2 = buf[pad(base + 2 * S)], a3 = buf[pad(base + 3 * S)];
+    if (!INV) {
+      a1 = cmul(a1, tw<false>(w1024, j * step));
+      a2 = cmul(a2, tw<false>(w1024, 2 * j * step));
+      a3 = cmul(a3, tw<false>(w1024, 3 * j * step));
+      dft4<false>(a0, a1, a2, a3);
+    } else {
+      dft4<true>(a0, a1, a2, a3);
+      a1 = cmul(a1, tw<true>(w1024, j * step));
+      a2 = cmul(a2, tw<true>(w1024, 2 * j * step));
+      a3 = cmul(a3, tw<true>(w1024, 3 * j * step));
+    }
+    buf[pad(base)] = a0;
+    buf[pad(base + S)] = a1;
+    buf[pad(base + 2 * S)] = a2;
+    buf[pad(base + 3 * S)] = a3;
+  }
+}
+
+// In-place radix-4 transform of 1024 points of one channel held by kTpc
+// threads: DIT from digit-reversed input to natural output (forward: stages
+// 0 + 1, 2 + 3, 4), or DIF from natural input to digit-reversed output
+// (inverse: stages 4 + 3, 2 + 1, 0).  Three passes through LDS, a workgroup
+// barrier after each.
 template <bool INV, int kTpc>
 __device__ __forceinline__ void fft1024(float2 *buf, const float2 *__restrict__ w1024, int tc) {
-#pragma unroll
-  for (int st = 0; st < 5; ++st) {
-    const int s = INV ? 4 - st : st;     // DIF runs the spans from 256 down to 1
-    const int S = 1 << (2 * s);          // span: the sub-transforms combined have length 4 S
-    const int step = kN2 / (4 * S);      // W_(4S)^j = W_1024^(j step)
-#pragma unroll
-    for (int u = 0; u < 256 / kTpc; ++u) {
-      const int b = tc + u * kTpc;       // butterfly 0 .. 255
-      const int j = b & (S - 1), g = b >> (2 * s);
-      const int base = g * 4 * S + j;
-      float2 a0 = buf[pad(base)], a1 = buf[pad(base + S)], a2 = buf[pad(base + 2 * S)], a3 = buf[pad(base + 3 * S)];
-      if (!INV) {  // DIT: twiddle, then the 4-point transform
-        a1 = cmul(a1, tw<INV>(w1024, j * step));
-        a2 = cmul(a2, tw<INV>(w1024, 2 * j * step));
-        a3 = cmul(a3, tw<INV>(w1024, 3 * j * step));
-        dft4<INV>(a0, a1, a2, a3);
-      } else {     // DIF: the 4-point transform, then the twiddle
-        dft4<INV>(a0, a1, a2, a3);
-        a1 = cmul(a1, tw<INV>(w1024, j * step));
-        a2 = cmul(a2, tw<INV>(w1024, 2 * j * step));
-        a3 = cmul(a3, tw<INV>(w1024, 3 * j * step));
-      }
-      buf[pad(base)] = a0;
-      buf[pad(base + S)] = a1;
-      buf[pad(base + 2 * S)] = a2;
-      buf[pad(base + 3 * S)] = a3;
-    }
+  if constexpr (!INV) {
+    radix16<false, 0, kTpc>(buf, w1024, tc);
+    __syncthreads();
+    radix16<false, 2, kTpc>(buf, w1024, tc);
+    __syncthreads();
+    radix4<false, 4, kTpc>(buf, w1024, tc);
+    __syncthreads();
+  } else {
+    radix16<true, 3, kTpc>(buf, w1024, tc);
+    __syncthreads();
+    radix16<true, 1, kTpc>(buf, w1024, tc);
+    __syncthreads();
+    radix4<true, 0, kTpc>(buf, w1024, tc);
     __syncthreads();
   }
 }
