@@ -144,8 +144,11 @@ __device__ __forceinline__ double wave_sum_halving(const double (&gc)[NC]) {
 // forward recompute; the host selects it when every section is invertible
 // with |a2| >= 1/4 (first order: |a1| >= 1/2, b2 = 0), which bounds the
 // growth of rounding over a 16-row block by 2^16.
-template <int K, int L, bool UNIT, bool RECON>
-__global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
+// FULL: the window fills every block (n_t = NB L), so no row is past its
+// end and the row loops run without a per-row validity branch (which costs
+// the exec-mask updates and the register copies at every join).
+template <int K, int L, bool UNIT, bool RECON, bool FULL>
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(3))) adj_kernel(AdjParams) {
   constexpr int NS = 2 * K, NSP = NS + 1, NC = 5 * K;
   constexpr bool kSgprLevels = K <= 4;
   extern __shared__ double lds[];
@@ -266,7 +269,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
       else
         yd = widen<2>(yk[K - 1][j]);
       const double e = yd * yd;
-      if (j < nv) {
+      if (FULL || j < nv) {
         s_loc = fma(asd, s_loc, e);
         l_loc = fma(ald, l_loc, e);
       }
@@ -338,7 +341,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
 #pragma unroll
     for (int j = 0; j < L; ++j) {
       float al = 0.0f, be = 0.0f;
-      if (j < nv) sf.step(S, Lg, widen<3>(yout(j)), widen<4>(gv[j]), g0 + row0 + j, al, be);
+      if (FULL || j < nv) sf.step(S, Lg, widen<3>(yout(j)), widen<4>(gv[j]), g0 + row0 + j, al, be);
       gv[j] = al;
       bt[j] = be;
       __builtin_amdgcn_sched_barrier(0);
@@ -358,7 +361,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     // from the block end to its start, from zero (or the handed-in state)
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
-      if (j < nv) (void)sb.step(A, B, widen<5>(yout(j)), gv[j], bt[j]);
+      if (FULL || j < nv) (void)sb.step(A, B, widen<5>(yout(j)), gv[j], bt[j]);
       __builtin_amdgcn_sched_barrier(0);
     }
     cdouble *dp = as_const(q->dpow);
@@ -390,7 +393,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
       float v = 0.0f;
-      if (j < nv) v = (float)sb.step(Ax, Bx, widen<6>(yout(j)), gv[j], bt[j]);
+      if (FULL || j < nv) v = (float)sb.step(Ax, Bx, widen<6>(yout(j)), gv[j], bt[j]);
       yb[j] = v;
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -412,7 +415,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
     // -a1, -a2, so ys is ybar - a1 u1 - a2 u2)
 #pragma unroll
     for (int j = L - 1; j >= 0; --j) {
-      if (j < nv) {
+      if (FULL || j < nv) {
         double ybar = (double)yb[j];
 #pragma unroll
         for (int k = K - 1; k >= 0; --k) {
@@ -564,8 +567,15 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) adj_kernel(AdjParams) {
 template <int K, int L, bool U, bool RC>
 hipError_t launch_u(const AdjParams &p, hipStream_t stream) {
   const size_t lds = adj_lds_bytes(K, p.nw, p.n_lev);
-  hipLaunchKernelGGL((adj_kernel<K, L, U, RC>), dim3((unsigned)grid_for(p.per_xcd)),
-                     dim3((unsigned)(p.nw * kWave)), lds, stream, p);
+  const dim3 grid((unsigned)grid_for(p.per_xcd)), block((unsigned)(p.nw * kWave));
+  if constexpr (L == 16 && U) {  // the full-window variant for the default Butterworth path
+    const int nb = p.nw * (kWave >> p.cw_log2);
+    if (p.n_t == nb * L) {
+      hipLaunchKernelGGL((adj_kernel<K, L, U, RC, true>), grid, block, lds, stream, p);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((adj_kernel<K, L, U, RC, false>), grid, block, lds, stream, p);
   return hipGetLastError();
 }
 
