@@ -147,8 +147,12 @@ __device__ __forceinline__ double wave_sum_halving(const double (&gc)[NC]) {
 // FULL: the window fills every block (n_t = NB L), so no row is past its
 // end and the row loops run without a per-row validity branch (which costs
 // the exec-mask updates and the register copies at every join).
-template <int K, int L, bool UNIT, bool RECON, bool FULL>
+// RC: 0 stores the section outputs, 1 rebuilds them (every section of
+// second order), 2 rebuilds them with first-order sections among them (a
+// per-section test on the host's mask).
+template <int K, int L, bool UNIT, int RC, bool FULL>
 __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(3))) adj_kernel(AdjParams) {
+  constexpr bool RECON = RC != 0;
   constexpr int NS = 2 * K, NSP = NS + 1, NC = 5 * K;
   constexpr bool kSgprLevels = K <= 4;
   extern __shared__ double lds[];
@@ -491,7 +495,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
           const double z1a = zr[2 * k], z2a = zr[2 * k + 1];
           const bool unit = UNIT && k > 0;
           double y;
-          if ((first_order >> k) & 1) {  // a2 = b2 = 0: z1' = b1 v - a1 y, z2 = 0
+          if (RC == 2 && ((first_order >> k) & 1)) {  // a2 = b2 = 0: z1' = b1 v - a1 y, z2 = 0
             y = fma(-coef[5 * k + 1], v, z1a) * ri[k];
             zr[2 * k] = unit ? y - v : fma(-coef[5 * k + 0], v, y);
             zr[2 * k + 1] = 0.0;
@@ -564,11 +568,11 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
   }
 }
 
-template <int K, int L, bool U, bool RC>
+template <int K, int L, bool U, int RC>
 hipError_t launch_u(const AdjParams &p, hipStream_t stream) {
   const size_t lds = adj_lds_bytes(K, p.nw, p.n_lev);
   const dim3 grid((unsigned)grid_for(p.per_xcd)), block((unsigned)(p.nw * kWave));
-  if constexpr (L == 16 && U) {  // the full-window variant for the default Butterworth path
+  if constexpr (L == 16 && U && RC == 1) {  // the full-window variant for the default Butterworth path
     const int nb = p.nw * (kWave >> p.cw_log2);
     if (p.n_t == nb * L) {
       hipLaunchKernelGGL((adj_kernel<K, L, U, RC, true>), grid, block, lds, stream, p);
@@ -582,9 +586,13 @@ hipError_t launch_u(const AdjParams &p, hipStream_t stream) {
 template <int K, int L>
 hipError_t launch_one(const AdjParams &p, bool unit, hipStream_t stream) {
   if constexpr (K >= 2 && L == 16) {  // the default adjoint block only
-    if (unit) return p.recon ? launch_u<K, L, true, true>(p, stream) : launch_u<K, L, true, false>(p, stream);
+    if (unit) {
+      if (p.recon == 1) return launch_u<K, L, true, 1>(p, stream);
+      return p.recon ? launch_u<K, L, true, 2>(p, stream) : launch_u<K, L, true, 0>(p, stream);
+    }
   }
-  return p.recon ? launch_u<K, L, false, true>(p, stream) : launch_u<K, L, false, false>(p, stream);
+  if (p.recon == 1) return launch_u<K, L, false, 1>(p, stream);
+  return p.recon ? launch_u<K, L, false, 2>(p, stream) : launch_u<K, L, false, 0>(p, stream);
 }
 
 template <int L>

@@ -1067,7 +1067,7 @@ filark_status adjoint_run(filark_sos_t sos, filark_stalta_t sl, const double *ta
   p.Pw = sos->adj.d + sos->adj.off_P;
   p.rinv = sos->adj.d + sos->adj.off_R;
   p.first_order = sos->cas.first_order_bits();
-  p.recon = sos->cas.invertible() ? 1 : 0;
+  p.recon = sos->cas.invertible() ? (p.first_order ? 2 : 1) : 0;
   p.dpow = sl->adj.d;
   p.cs = 1.0 / (double)sl->nsta;
   p.cl = 1.0 / (double)sl->nlta;

@@ -81,7 +81,8 @@ struct AdjParams {
   const double *coef, *G, *Pw;  // forward tables (as FwdParams)
   const double *rinv;  // [K]: 1 / (-a2), or 1 / (-a1) for a first-order section (rebuilding variant)
   int32_t first_order; // bit k: section k is first order (a2 = b2 = 0)
-  int32_t recon;       // 1: section signals rebuilt backwards instead of stored (adj_kernel RECON)
+  int32_t recon;       // section signals: 0 stored, 1 rebuilt backwards (second-order sections only),
+                       // 2 rebuilt with first-order sections among them (adj_kernel RC)
   const double *dpow;           // [n_lev][2] decays^(L 2^k), then [L + 1][2] decays^m
   double asd, ald;     // 1 - 1/nsta, 1 - 1/nlta
   double cs, cl;       // 1/nsta, 1/nlta
