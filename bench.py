@@ -505,6 +505,20 @@ def fir_fft_case(F, torch, dev, x, chunk, M, steps, parity):
                        "algorithmic_gbs": gbs, "hbm_frac": gbs / 8000.0}
         if method == "direct":
             out[method]["tflops"] = n_t * n_ch * 2 * M / (ms / 1e3) / 1e12
+        else:
+            # algorithmic flops of the FFT method: per channel and 2048-row
+            # window, a forward and an inverse 1024-point complex transform
+            # (5 N log2 N each) and the spectral pass (~8 per point pair and
+            # product); windows per call = ceil(rows / (2049 - M))
+            win = -(-chunk // (2049 - M)) * (n_t // chunk) + (-(-(n_t % chunk) // (2049 - M)) if n_t % chunk else 0)
+            flops = n_ch * win * (2 * 5 * 1024 * 10 + 16 * 1024)
+            tf = flops / (ms / 1e3) / 1e12
+            out[method]["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                                       "kernel": "fir_fft_kernel<8, 512>",
+                                       "flops": {"achieved_tflops": tf, "peak_tflops": FP32_VALU_PEAK_TFLOPS,
+                                                 "frac": tf / FP32_VALU_PEAK_TFLOPS,
+                                                 "per_window_per_channel": 2 * 5 * 1024 * 10 + 16 * 1024}}
         if method == "fft" and parity:
             import oracle
 
