@@ -118,6 +118,46 @@ def test_tape_chain_matches_oracle_and_plain_adjoint(F, n_ch, splits):
     np.testing.assert_allclose(zend, zend0, rtol=0, atol=1e-6 * np.max(np.abs(zend0)))
 
 
+def _sos(kind):
+    orc = _orc()
+    if kind == "bp8":
+        return orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
+    if kind == "gain_moved":  # later sections no longer [1, b1, 1]: the general section step
+        sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0).copy()
+        sos[0, :3] *= 8.0
+        sos[2, :3] *= 0.125
+        return sos
+    if kind == "hp5":  # odd order: a first-order section among second-order ones
+        return orc.butter_sos(5, "highpass", 3.0, 0.0, 500.0)
+    return orc.butter_sos(2, "lowpass", 30.0, 0.0, 200.0)  # one section
+
+
+@pytest.mark.parametrize("kind", ["gain_moved", "hp5", "lp2"])
+def test_tape_chain_other_cascades(F, kind):
+    """The tape path for the other kernel variants: general numerators, a
+    first-order section (the rebuild's per-section test), one section; full
+    and partial windows, against the oracle's one-shot gradient."""
+    orc = _orc()
+    sos = _sos(kind)
+    n_ch, nsta, nlta = 29, 15, 150
+    splits = [(0, 1024), (1024, 1030), (1030, 2200)]
+    n_t = splits[-1][1]
+    g = torch.Generator(device="cuda").manual_seed(77)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    tgt = torch.rand((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32) * 3.0
+    scale = 1.0 / x.numel()
+    cf, zend, gx, adj, gs = _run(F, x, tgt, sos, nsta, nlta, splits, scale, True)
+    xh = x.cpu().numpy().astype(np.float64)
+    th = tgt.cpu().numpy().astype(np.float64)
+    y, zo = orc.sos_filter(sos, xh)
+    ocf, _, _ = orc.stalta(y, nsta, nlta)
+    assert max_rel_rms(cf, ocf) <= 1e-5
+    _, ogx, ogs, oadj = orc.stalta_grad(sos, xh, th, nsta, nlta, scale)
+    assert max_rel_rms(gx, ogx) <= 1e-5
+    assert float(np.linalg.norm(gs - ogs) / np.linalg.norm(ogs)) <= 1e-5
+    assert float(np.max(np.abs(adj - oadj)) / np.max(np.abs(oadj))) <= 1e-6
+
+
 def test_tape_bytes_and_errors(F):
     orc = _orc()
     sos = orc.butter_sos(8, "bandpass", 1.0, 100.0, 1500.0)
