@@ -259,7 +259,7 @@ struct filark_fir_state {
   int n_taps = 0, n_pad = 0;      // M and M padded to the tap chunk
   float *d_h = nullptr;           // [n_pad] FP32 taps, zero past M
   float *d_hist[2] = {};          // [max(M - 1, 1)][n_ch] each; d_ctl[0] names the current one
-  uint32_t *d_ctl = nullptr;      // [2]: [0] & 1 names the current history buffer
+  uint32_t *d_ctl = nullptr;      // [2]: [0] & 1 names the current history buffer; [1]: FFT workgroups done
   int rows = 0, waves = 1;        // output rows per wave (0: by launch), waves per workgroup
   int order = 2;                  // workgroup order: a channel slab per XCD, swept row block by row block
   int method = FILARK_FIR_DIRECT;
@@ -1889,8 +1889,7 @@ filark_status filark_fir_process(filark_fir_t st, const float *in, float *out, i
     if ((n_t + q.B - 1) / q.B > 65535) return fail(FILARK_EINVAL, "n_t too large for one FFT call");
     const int prev_dev = current_device();
     if (prev_dev != st->device) HIP_TRY(hipSetDevice(st->device));
-    hipError_t e = launch_fir_fft(q, stream);
-    if (e == hipSuccess) e = launch_fir_flip(st->d_ctl, stream);
+    hipError_t e = launch_fir_fft(q, stream);  // it also flips the current history buffer
     if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
     if (e != hipSuccess) return fail(FILARK_EHIP, "FFT launch failed: %s", hipGetErrorString(e));
     return FILARK_OK;

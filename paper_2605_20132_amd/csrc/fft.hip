@@ -23,7 +23,8 @@
 // host.  FP32 throughout (twiddles and H rounded from FP64); the error bound
 // is that of FP32 transforms, not the direct kernel's exact summation order.
 // The workgroups of the call's last block also write the new history (the
-// last M - 1 input rows) into the other history buffer as they load it.
+// last M - 1 input rows) into the other history buffer as they load it, and
+// the last workgroup to finish makes that buffer the current one.
 #include "device.h"
 #include "fir.h"
 
@@ -313,6 +314,16 @@ __attribute__((amdgpu_waves_per_eu(kThreads * 2 / (4 * 64)))) fir_fft_kernel(Fft
       __builtin_nontemporal_store((r & 1) ? v.y : v.x, p.y + t * p.n_ch + c);
     }
   }
+  // The call's last workgroup to finish names the other history buffer the
+  // current one and clears the count: every workgroup read the old name
+  // before its first barrier, and a graph replay finds the count at 0.
+  if (tid == 0) {
+    const uint32_t done = atomicAdd(p.ctl + 1, 1u);
+    if (done + 1 == p.total) {
+      atomicXor(p.ctl, 1u);
+      atomicExch(p.ctl + 1, 0u);
+    }
+  }
 }
 
 }  // namespace
@@ -324,8 +335,9 @@ hipError_t launch_fir_fft(const FftParams &p_in, hipStream_t stream) {
   const int thr = p.threads == 512 && ch == 8 ? 512 : 256;
   const int64_t n_blk = (p.n_t + p.B - 1) / p.B;
   const int64_t n_cg = (p.n_ch + ch - 1) / ch;
-  if (n_blk > 65535 || n_cg > ((int64_t)1 << 28)) return hipErrorInvalidValue;
+  if (n_blk > 65535 || n_cg > ((int64_t)1 << 28) || n_cg * n_blk >= ((int64_t)1 << 32)) return hipErrorInvalidValue;
   p.per_xcd = (int32_t)((n_cg + 7) / 8);
+  p.total = (uint32_t)(n_cg * n_blk);
   const dim3 grid((unsigned)(8 * p.per_xcd), (unsigned)n_blk);
   if (ch == 4)
     hipLaunchKernelGGL((fir_fft_kernel<4, 256>), grid, dim3(256), 0, stream, p);

@@ -52,13 +52,14 @@ struct FftParams {
   const float2 *tw;       // [1024] W_1024^j, then [1024] W_2048^k (FP32 of FP64 values)
   const float2 *H;        // [1025] the taps' 2048-point spectrum, scaled by 1 / 4096
   float *hist0, *hist1;   // history buffers [M - 1][n_ch] (as FirParams)
-  const uint32_t *ctl;
+  uint32_t *ctl;          // [0] & 1: the current history buffer; [1]: workgroups done (the last flips [0])
   int64_t n_ch, n_t;
   int32_t hm;             // M - 1
   int32_t B;              // output rows per block
   int32_t ch;             // channels per workgroup: 4 or 8
   int32_t threads;        // threads per workgroup: 256, or 512 with 8 channels
   int32_t per_xcd;        // channel groups per XCD slab (set by the launcher)
+  uint32_t total;         // workgroups that do work (set by the launcher)
 };
 hipError_t launch_fir_fft(const FftParams &p, hipStream_t stream);
 
