@@ -179,3 +179,13 @@ def test_tape_bytes_and_errors(F):
     st.set_adjoint_tile(8, 4, 8)
     sl.set_adjoint_tile(8, 4, 8)
     assert F.adjoint_tape_bytes(st, sl, 1000) == 4 * slot
+    # empty chunks: nothing is written or read, the state stays
+    assert F.adjoint_tape_bytes(st, sl, 0) == 0
+    tape = torch.full((slot,), 7, dtype=torch.uint8, device="cuda")
+    z0 = st.get_state()
+    F.sos_stalta_process_tape(st, sl, torch.zeros((0, n_ch), device="cuda"), tape=tape)
+    gx, adj, gs = F.sos_stalta_adjoint_tape(st, sl, tape, torch.zeros((0, n_ch), device="cuda"),
+                                            torch.zeros((0, n_ch), device="cuda"))
+    torch.cuda.synchronize()
+    assert bool((tape == 7).all()) and not adj.any() and not gs.any()
+    np.testing.assert_array_equal(st.get_state(), z0)
