@@ -288,25 +288,26 @@ filark_status filark_sos_stalta_adjoint(filark_sos_t sos, filark_stalta_t sl, co
  *                64 rows that divides 2048 (the default adjoint tile is).
  *   _process_tape  filark_sos_stalta_process (cf required, y optional), run
  *                with 64-row blocks, that also writes the chunk's tape into
- *                `tape` (device, caller-owned, _tape_bytes bytes for this
- *                n_t).  The objects' state advances as in the plain call; cf
+ *                `tape` (device, caller-owned, `tape_bytes` long: at least
+ *                _tape_bytes for this n_t, else FILARK_EINVAL).  The objects' state advances as in the plain call; cf
  *                and the state agree with it to rounding (a different block
  *                length sums in a different order).  Asynchronous on `stream`.
  *   _adjoint_tape  filark_sos_stalta_adjoint over the same chunk from its
  *                tape (arguments as there); the objects only supply the
  *                filter, the windows and the tiles, and their state is
  *                neither read nor written, so no checkpoint needs restoring.
- *                The adjoint tile must be the one the tape was written with.
+ *                The adjoint tile must be the one the tape was written with
+ *                (a tape shorter than the current tile needs is refused).
  * Errors: FILARK_EINVAL, FILARK_ESHAPE, FILARK_EHIP.
  */
 filark_status filark_adjoint_tape_bytes(filark_sos_t sos, filark_stalta_t sl, int64_t n_t, size_t *bytes);
 filark_status filark_sos_stalta_process_tape(filark_sos_t sos, filark_stalta_t sl, const float *x, float *y,
-                                             float *cf, void *tape, int64_t n_ch, int64_t n_t,
+                                             float *cf, void *tape, size_t tape_bytes, int64_t n_ch, int64_t n_t,
                                              hipStream_t stream);
 filark_status filark_sos_stalta_adjoint_tape(filark_sos_t sos, filark_stalta_t sl, const void *tape,
-                                             const float *x, const float *g, int mode, double scale, float *gx,
-                                             double *adj, double *gsos, int64_t n_ch, int64_t n_t,
-                                             hipStream_t stream);
+                                             size_t tape_bytes, const float *x, const float *g, int mode,
+                                             double scale, float *gx, double *adj, double *gsos, int64_t n_ch,
+                                             int64_t n_t, hipStream_t stream);
 
 /*
  * Batched filtering of many independent streams in one launch (the stateful

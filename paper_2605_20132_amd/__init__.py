@@ -83,9 +83,9 @@ def lib():
     L.filark_sos_stalta_adjoint.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp, i64,
                                             i64, vp]
     L.filark_adjoint_tape_bytes.argtypes = [vp, vp, i64, ctypes.POINTER(ctypes.c_size_t)]
-    L.filark_sos_stalta_process_tape.argtypes = [vp, vp, vp, vp, vp, vp, i64, i64, vp]
-    L.filark_sos_stalta_adjoint_tape.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp,
-                                                 i64, i64, vp]
+    L.filark_sos_stalta_process_tape.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, i64, i64, vp]
+    L.filark_sos_stalta_adjoint_tape.argtypes = [vp, vp, vp, ctypes.c_size_t, vp, vp, ctypes.c_int, ctypes.c_double,
+                                                 vp, vp, vp, i64, i64, vp]
     L.filark_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), vp]
     L.filark_batch_bind.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i64), vp]
     L.filark_batch_launch.argtypes = [vp, vp]
@@ -420,12 +420,12 @@ def sos_stalta_process_tape(sos: SOSState, sl: StaLtaState, x, tape=None, y=None
         cf = torch.empty_like(x)
     if tape is None:
         tape = torch.empty(adjoint_tape_bytes(sos, sl, n_t), dtype=torch.uint8, device=x.device)
-    if not tape.is_cuda or not tape.is_contiguous() or tape.numel() * tape.element_size() < adjoint_tape_bytes(
-            sos, sl, n_t):
-        raise FilarkError(EINVAL, "tape must be a contiguous CUDA tensor of adjoint_tape_bytes bytes")
+    if not tape.is_cuda or not tape.is_contiguous():
+        raise FilarkError(EINVAL, "tape must be a contiguous CUDA tensor")
     _check(lib().filark_sos_stalta_process_tape(sos.handle, sl.handle, _dev_f32(x, "x"),
                                                 _dev_f32(y, "y") if y is not None else None, _dev_f32(cf, "cf"),
-                                                ctypes.c_void_p(tape.data_ptr()), n_ch, n_t, _stream(stream)))
+                                                ctypes.c_void_p(tape.data_ptr()), tape.numel() * tape.element_size(),
+                                                n_ch, n_t, _stream(stream)))
     return y, cf, tape
 
 
@@ -448,11 +448,11 @@ def sos_stalta_adjoint_tape(sos: SOSState, sl: StaLtaState, tape, x, g, gx=None,
             raise FilarkError(EINVAL, f"{name} must be a contiguous float64 CUDA tensor")
     if adj.shape != (2 * K + 2, n_ch) or gsos.shape != (K, 5):
         raise FilarkError(EINVAL, "adj must be [2K+2, n_ch] and gsos [K, 5]")
-    if not tape.is_cuda or not tape.is_contiguous() or tape.numel() * tape.element_size() < adjoint_tape_bytes(
-            sos, sl, n_t):
-        raise FilarkError(EINVAL, "tape must be a contiguous CUDA tensor of adjoint_tape_bytes bytes")
+    if not tape.is_cuda or not tape.is_contiguous():
+        raise FilarkError(EINVAL, "tape must be a contiguous CUDA tensor")
     m = {"grad": ADJ_GRAD, "mse": ADJ_MSE}[mode]
     _check(lib().filark_sos_stalta_adjoint_tape(sos.handle, sl.handle, ctypes.c_void_p(tape.data_ptr()),
+                                                tape.numel() * tape.element_size(),
                                                 _dev_f32(x, "x"), _dev_f32(g, "g"), m, float(scale),
                                                 _dev_f32(gx, "gx"), ctypes.c_void_p(adj.data_ptr()),
                                                 ctypes.c_void_p(gsos.data_ptr()), n_ch, n_t, _stream(stream)))

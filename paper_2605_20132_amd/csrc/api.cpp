@@ -949,6 +949,12 @@ size_t ck_slot_doubles(const filark_sos_state *sos, int64_t n_ch) {
 // registers every workgroup of a 6000-channel chunk is resident at once).
 Tile tape_tile(const filark_sos_state *sos, int64_t) { return sos->ckp.tile; }
 
+// Bytes of the tape of a chunk of n_t rows: one slot per adjoint window.
+size_t tape_need(const filark_sos_state *sos, int64_t n_ch, int64_t n_t) {
+  const int64_t rows = adjoint_rows(sos, n_ch);
+  return rows > 0 ? (size_t)((n_t + rows - 1) / rows) * ck_slot_doubles(sos, n_ch) * sizeof(double) : 0;
+}
+
 // Why a tape cannot be used with these objects and this channel count, or null.
 const char *tape_unusable(const filark_sos_state *sos, const filark_stalta_state *sl, int64_t n_ch) {
   const Tile tt = tape_tile(sos, n_ch);
@@ -1115,13 +1121,12 @@ filark_status filark_adjoint_tape_bytes(filark_sos_t sos, filark_stalta_t sl, in
   if (sos->n_ch != sl->n_ch) return fail(FILARK_ESHAPE, "the states' channel counts differ");
   const char *why = tape_unusable(sos, sl, sos->n_ch);
   if (why) return fail(FILARK_EINVAL, "no tape: %s", why);
-  const int64_t rows = adjoint_rows(sos, sos->n_ch);
-  *bytes = (size_t)((n_t + rows - 1) / rows) * ck_slot_doubles(sos, sos->n_ch) * sizeof(double);
+  *bytes = tape_need(sos, sos->n_ch, n_t);
   return FILARK_OK;
 }
 
 filark_status filark_sos_stalta_process_tape(filark_sos_t sos, filark_stalta_t sl, const float *x, float *y,
-                                             float *cf, void *tape, int64_t n_ch, int64_t n_t,
+                                             float *cf, void *tape, size_t tape_bytes, int64_t n_ch, int64_t n_t,
                                              hipStream_t stream) {
   if (!sos || !sl) return fail(FILARK_EINVAL, "null state");
   if (sos->device != sl->device) return fail(FILARK_EINVAL, "states live on different devices");
@@ -1132,6 +1137,8 @@ filark_status filark_sos_stalta_process_tape(filark_sos_t sos, filark_stalta_t s
   if (y && (const void *)y == (const void *)cf) return fail(FILARK_EINVAL, "y and cf must differ");
   const char *why = tape_unusable(sos, sl, n_ch);
   if (why) return fail(FILARK_EINVAL, "no tape: %s", why);
+  const size_t need = tape_need(sos, n_ch, n_t);
+  if (tape_bytes < need) return fail(FILARK_EINVAL, "tape of %zu bytes, %zu needed", tape_bytes, need);
   const Tile tt = tape_tile(sos, n_ch);
   const int K = sos->cas.K;
   filark_status rc = check_lds(fwd_lds_bytes(K, tt.waves, tt.levels(), tt.group), tt, K, sos->device);
@@ -1148,14 +1155,16 @@ filark_status filark_sos_stalta_process_tape(filark_sos_t sos, filark_stalta_t s
 }
 
 filark_status filark_sos_stalta_adjoint_tape(filark_sos_t sos, filark_stalta_t sl, const void *tape,
-                                             const float *x, const float *g, int mode, double scale, float *gx,
-                                             double *adj, double *gsos, int64_t n_ch, int64_t n_t,
-                                             hipStream_t stream) {
+                                             size_t tape_bytes, const float *x, const float *g, int mode,
+                                             double scale, float *gx, double *adj, double *gsos, int64_t n_ch,
+                                             int64_t n_t, hipStream_t stream) {
   if (!sos || !sl) return fail(FILARK_EINVAL, "null state");
   if (n_t > 0 && !tape) return fail(FILARK_EINVAL, "null tape");
-  if (sos->n_ch == n_ch && sl->n_ch == n_ch) {
+  if (sos->n_ch == n_ch && sl->n_ch == n_ch && n_t > 0) {
     const char *why = tape_unusable(sos, sl, n_ch);
     if (why) return fail(FILARK_EINVAL, "no tape: %s", why);
+    const size_t need = tape_need(sos, n_ch, n_t);
+    if (tape_bytes < need) return fail(FILARK_EINVAL, "tape of %zu bytes, %zu needed", tape_bytes, need);
   }
   return adjoint_run(sos, sl, static_cast<const double *>(tape), x, g, mode, scale, gx, adj, gsos, n_ch, n_t,
                      stream);

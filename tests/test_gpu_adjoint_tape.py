@@ -170,6 +170,17 @@ def test_tape_bytes_and_errors(F):
     x = torch.zeros((100, n_ch), device="cuda")
     with pytest.raises(F.FilarkError):  # a tape too small
         F.sos_stalta_process_tape(st, sl, x, tape=torch.empty(10, dtype=torch.uint8, device="cuda"))
+    # a tape written with 512-row windows, read after the adjoint tile moved
+    # to 256-row windows: twice the slots are needed, so it is refused
+    x2 = torch.zeros((1000, n_ch), device="cuda")
+    _, _, tp = F.sos_stalta_process_tape(st, sl, x2)
+    assert tp.numel() == 2 * slot
+    st.set_adjoint_tile(8, 4, 8)
+    sl.set_adjoint_tile(8, 4, 8)
+    with pytest.raises(F.FilarkError):
+        F.sos_stalta_adjoint_tape(st, sl, tp, x2, x2)
+    st.set_adjoint_tile(16, 4, 8)
+    sl.set_adjoint_tile(16, 4, 8)
     # 384-row adjoint windows do not divide the tape's 2048-row launch windows
     st.set_adjoint_tile(16, 3, 8)
     sl.set_adjoint_tile(16, 3, 8)
