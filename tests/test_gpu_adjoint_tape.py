@@ -200,3 +200,60 @@ def test_tape_bytes_and_errors(F):
     torch.cuda.synchronize()
     assert bool((tape == 7).all()) and not adj.any() and not gs.any()
     np.testing.assert_array_equal(st.get_state(), z0)
+
+
+def test_tape_step_in_a_graph(F):
+    """A whole forward + adjoint step on the tape path (state reset, forward
+    with tapes over every chunk, adjoint chain) captured in a HIP graph after
+    one eager step, replayed three times with eager work in between: every
+    replay equals the eager step bit for bit."""
+    orc = _orc()
+    sos = _sos("bp8")
+    n_ch, nsta, nlta = 40, 30, 300
+    splits = [(0, 1000), (1000, 2100), (2100, 2600)]
+    n_t, K = splits[-1][1], sos.shape[0]
+    g = torch.Generator(device="cuda").manual_seed(91)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    tgt = torch.rand((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    st = F.SOSState(sos, n_ch)
+    sl = F.StaLtaState(float(nsta), float(nlta), 1.0, n_ch)
+    z0, s0 = st.save(), sl.save()
+    tapes = [torch.empty(F.adjoint_tape_bytes(st, sl, b - a), dtype=torch.uint8, device="cuda") for a, b in splits]
+    cf, gx = torch.empty_like(x), torch.empty_like(x)
+    adj = torch.zeros((2 * K + 2, n_ch), dtype=torch.float64, device="cuda")
+    gs = torch.zeros((K, 5), dtype=torch.float64, device="cuda")
+
+    def step(stream=None):
+        st.load(z0, stream=stream)
+        sl.load(s0, stream=stream)
+        for i, (a, b) in enumerate(splits):
+            F.sos_stalta_process_tape(st, sl, x[a:b], tape=tapes[i], cf=cf[a:b], stream=stream)
+        adj.zero_()
+        gs.zero_()
+        for i in reversed(range(len(splits))):
+            a, b = splits[i]
+            F.sos_stalta_adjoint_tape(st, sl, tapes[i], x[a:b], tgt[a:b], gx[a:b], adj, gs, mode="mse",
+                                      scale=1.0 / x.numel(), stream=stream)
+
+    step()
+    torch.cuda.synchronize()
+    ref = (cf.clone(), gx.clone(), adj.clone(), gs.clone())
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            step(stream=s)
+    torch.cuda.synchronize()
+    for r in range(3):
+        cf.zero_()
+        gx.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for got, want in zip((cf, gx, adj, gs), ref):
+            assert torch.equal(got, want), f"replay {r}"
+    _, ogx, ogs, _ = orc.stalta_grad(sos, x.cpu().numpy().astype(np.float64),
+                                     tgt.cpu().numpy().astype(np.float64), nsta, nlta, 1.0 / x.numel())
+    assert max_rel_rms(gx.cpu().numpy(), ogx) <= 1e-5
+    assert float(np.linalg.norm(gs.cpu().numpy() - ogs) / np.linalg.norm(ogs)) <= 1e-5

@@ -123,28 +123,41 @@ def test_config5_full_size_forward_adjoint(F):
     tgt = torch.from_numpy(tgt_h.astype(np.float32)).to("cuda")
     scale = 1.0 / (n_ch * n_t)
 
-    st = F.SOSState(sos, n_ch)
-    sl = F.StaLtaState(w.sta_s, w.lta_s, w.fs, n_ch)
-    cks = []
-    for a in range(0, n_t, w.chunk):
-        cks.append((st.save(), sl.save()))
-        F.sos_stalta_process(st, sl, x[a:a + w.chunk], write_y=False)
     K = sos.shape[0]
-    gx = torch.empty_like(x)
-    adj = torch.zeros((2 * K + 2, n_ch), dtype=torch.float64, device="cuda")
-    gs = torch.zeros((K, 5), dtype=torch.float64, device="cuda")
-    for i in reversed(range(len(cks))):
-        a = i * w.chunk
-        st.load(cks[i][0])
-        sl.load(cks[i][1])
-        F.sos_stalta_adjoint(st, sl, x[a:a + w.chunk], tgt[a:a + w.chunk], gx[a:a + w.chunk], adj, gs,
-                             mode="mse", scale=scale)
-    torch.cuda.synchronize()
-    st.check()
     tq = tgt.cpu().numpy().astype(np.float64)  # the exact target the GPU saw
     _, ogx, ogs, _ = orc.stalta_grad(sos, xh, tq, nsta, nlta, scale)
-    ex = max_rel_rms(gx.cpu().numpy(), ogx)
-    es = float(np.linalg.norm(gs.cpu().numpy() - ogs) / np.linalg.norm(ogs))
-    print(f"6000 x 30000 fwd+adjoint: dL/dx {ex:.2e} dL/dtheta {es:.2e}")
-    assert ex <= 1e-5
-    assert es <= 1e-5
+    # both ways into the adjoint: state checkpoints per chunk, and the
+    # forward's tape (the path the benchmark times)
+    for path in ("checkpoints", "tape"):
+        st = F.SOSState(sos, n_ch)
+        sl = F.StaLtaState(w.sta_s, w.lta_s, w.fs, n_ch)
+        cks = []
+        for a in range(0, n_t, w.chunk):
+            if path == "tape":
+                cks.append(F.sos_stalta_process_tape(st, sl, x[a:a + w.chunk])[2])
+            else:
+                cks.append((st.save(), sl.save()))
+                F.sos_stalta_process(st, sl, x[a:a + w.chunk], write_y=False)
+        gx = torch.empty_like(x)
+        adj = torch.zeros((2 * K + 2, n_ch), dtype=torch.float64, device="cuda")
+        gs = torch.zeros((K, 5), dtype=torch.float64, device="cuda")
+        for i in reversed(range(len(cks))):
+            a = i * w.chunk
+            if path == "tape":
+                F.sos_stalta_adjoint_tape(st, sl, cks[i], x[a:a + w.chunk], tgt[a:a + w.chunk], gx[a:a + w.chunk],
+                                          adj, gs, mode="mse", scale=scale)
+            else:
+                st.load(cks[i][0])
+                sl.load(cks[i][1])
+                F.sos_stalta_adjoint(st, sl, x[a:a + w.chunk], tgt[a:a + w.chunk], gx[a:a + w.chunk], adj, gs,
+                                     mode="mse", scale=scale)
+        torch.cuda.synchronize()
+        st.check()
+        ex = max_rel_rms(gx.cpu().numpy(), ogx)
+        es = float(np.linalg.norm(gs.cpu().numpy() - ogs) / np.linalg.norm(ogs))
+        print(f"6000 x 30000 fwd+adjoint ({path}): dL/dx {ex:.2e} dL/dtheta {es:.2e}")
+        assert ex <= 1e-5
+        assert es <= 1e-5
+        st.close()
+        sl.close()
+        del cks, gx
