@@ -48,8 +48,11 @@ constexpr uint32_t kOffInvalid = 0x80000000u;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, int range) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, range, 0x00020000);
 }
+// NT: the non-temporal hint, for inputs read once (the lines are not kept
+// for reuse in L2).
+template <bool NT = false>
 __device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, 0));
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, 0, NT ? 2 : 0));
 }
 // NT: the non-temporal hint, for outputs never read again.  It pays where a
 // workgroup writes at least 64 contiguous bytes of a row (the lines go out

@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) ema_kernel(EmaParams) {
     const __amdgpu_buffer_rsrc_t rx = rsrc(p->x, p->range);
     const uint32_t rb = fresh(rowb);
 #pragma unroll
-    for (int j = 0; j < L; ++j) xv[j] = buf_ld(rx, vo + (uint32_t)j * rb);
+    for (int j = 0; j < L; ++j) xv[j] = buf_ld<true>(rx, vo + (uint32_t)j * rb);  // read once: non-temporal
   }
   __syncthreads();
   const double avg_in = avg_x[cl];

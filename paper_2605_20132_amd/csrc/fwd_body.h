@@ -310,8 +310,10 @@ struct Levels {
   }
 };
 
-// Loads of channel group g's window into xv (issued, not waited for).
-template <int L, bool REV>
+// Loads of channel group g's window into xv (issued, not waited for); with
+// NT (groups of 16 channels or more, 64-byte row pieces) they carry the
+// non-temporal hint, as the stores do: the signal is read once.
+template <int L, bool REV, bool NT>
 __device__ __forceinline__ void fwd_load(PSrc ps, int g, float (&xv)[L]) {
   kparams_t p = ps.get();
   const int lane = threadIdx.x & (kWave - 1);
@@ -329,7 +331,7 @@ __device__ __forceinline__ void fwd_load(PSrc ps, int g, float (&xv)[L]) {
     const __amdgpu_buffer_rsrc_t rx = rsrc(ps.get()->x, ps.get()->range);
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-      xv[j] = buf_ld(rx, rw.off(j));
+      xv[j] = buf_ld<NT>(rx, rw.off(j));
       if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
   } else {
@@ -337,7 +339,7 @@ __device__ __forceinline__ void fwd_load(PSrc ps, int g, float (&xv)[L]) {
     const RowBuf rb{(const char *)q->x, (uint32_t)q->range, fresh((uint32_t)q->n_ch * 4u)};
 #pragma unroll
     for (int j = 0; j < L; ++j) {
-      xv[j] = buf_ld(rb.at(j), rw.vo);
+      xv[j] = buf_ld<NT>(rb.at(j), rw.vo);
       if ((j & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -548,7 +550,7 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   sa.read(ps, g);
   tb.read(ps);
   float xv[L];
-  fwd_load<L, REV>(ps, g, xv);
+  fwd_load<L, REV, NT>(ps, g, xv);
   warm_g<K, L>(ps);
   sa.write(ps, m);
   tb.write(ps, m);

@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) trig_kernel(TrigParams) {
     const uint32_t rowb = (uint32_t)n_ch * 4u;
     const uint32_t vo = cval ? (uint32_t)(((int64_t)row0 * n_ch + c) * 4) : kOffInvalid;
 #pragma unroll
-    for (int j = 0; j < L; ++j) xv[j] = buf_ld(rx, vo + (uint32_t)j * rowb);
+    for (int j = 0; j < L; ++j) xv[j] = buf_ld<true>(rx, vo + (uint32_t)j * rowb);  // read once: non-temporal
   }
   __syncthreads();  // workgroup barrier with every wave's memory reads complete
   const int s_in = s_x[cl];
