@@ -212,7 +212,7 @@ filark_status filark_state_set(void *st, int kind, const void *host_buf, size_t 
  * waves * 64 / group blocks of `block` samples per lane; longer chunks run
  * window by window.
  *   kind FILARK_STATE_SOS / _STALTA (forward): block 32, 48 or 64, default 48 x 8 x 16;
- *   kind FILARK_TILE_SOS_ADJOINT / _STALTA_ADJOINT: block 8 or 16, default 16 x 8 x 8;
+ *   kind FILARK_TILE_SOS_ADJOINT / _STALTA_ADJOINT: block 8 or 16, default 16 x 4 x 8;
  *   waves 1 .. 8;  group 4, 8, 16, 32 or 64.
  * The SOS and STA/LTA states used together must have equal shapes.  _set
  * synchronises `stream` and rebuilds the scan tables.  FILARK_EINVAL for a
@@ -220,6 +220,20 @@ filark_status filark_state_set(void *st, int kind, const void *host_buf, size_t 
  */
 filark_status filark_tile_set(void *st, int kind, int block, int waves, int group, hipStream_t stream);
 filark_status filark_tile_get(const void *st, int kind, int *block, int *waves, int *group);
+
+/*
+ * Most adjoint windows that one launch of the adjoint kernel takes (0, the
+ * default: no limit; 1: one launch per window).  With the default adjoint
+ * tile and a cascade whose sections after the first have numerators
+ * [1, +-2, 1] and |a2| >= 1/4 (every Butterworth design), the full windows
+ * of a chunk run in one launch: each workgroup keeps its channels from
+ * window to window, hands the adjoint state on through LDS and loads the
+ * next window's input while the current one runs.  Results are bit-identical
+ * for every value (the windows' arithmetic and its order do not change); the
+ * limit exists to measure and test that.  Takes effect at the next adjoint
+ * call.  FILARK_EINVAL for a null state or a negative value.
+ */
+filark_status filark_adjoint_windows_set(filark_sos_t sos, int max_windows);
 
 /*
  * Tile autotuner: times the forward kernel of a scratch state with the same

@@ -31,7 +31,7 @@ EXPORTS = (
     "filark_sos_design", "filark_sos_init", "filark_sos_process", "filark_stalta_init",
     "filark_stalta_process", "filark_sos_stalta_process", "filark_state_get", "filark_state_set",
     "filark_check", "filark_sos_destroy", "filark_stalta_destroy", "filark_last_error",
-    "filark_version", "filark_tile_set", "filark_tile_get", "filark_state_bytes", "filark_state_save",
+    "filark_version", "filark_tile_set", "filark_tile_get", "filark_adjoint_windows_set", "filark_state_bytes", "filark_state_save",
     "filark_state_load", "filark_sos_stalta_adjoint", "filark_adjoint_tape_bytes",
     "filark_sos_stalta_process_tape", "filark_sos_stalta_adjoint_tape", "filark_batch_create", "filark_batch_bind",
     "filark_batch_launch", "filark_batch_capture", "filark_autotune", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
@@ -76,6 +76,7 @@ def lib():
     L.filark_check.argtypes = [vp, ctypes.c_int, vp]
     ip = ctypes.POINTER(ctypes.c_int)
     L.filark_tile_set.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+    L.filark_adjoint_windows_set.argtypes = [vp, ctypes.c_int]
     L.filark_tile_get.argtypes = [vp, ctypes.c_int, ip, ip, ip]
     L.filark_state_bytes.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
     L.filark_state_save.argtypes = [vp, ctypes.c_int, vp, vp]
@@ -233,6 +234,11 @@ class SOSState:
         b, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _check(lib().filark_tile_get(self._h, TILE_SOS_ADJOINT, ctypes.byref(b), ctypes.byref(w), ctypes.byref(g)))
         return b.value, w.value, g.value
+
+    def set_adjoint_windows(self, max_windows: int):
+        """Most adjoint windows per kernel launch (0: no limit, 1: one launch
+        per window); results are bit-identical for every value."""
+        _check(lib().filark_adjoint_windows_set(self._h, int(max_windows)))
 
     def state_bytes(self) -> int:
         n = ctypes.c_size_t()

@@ -40,12 +40,12 @@ namespace filark {
 // LDS: exchanges [nw * 64][2] and [nw * 64][2K + 1], level matrices
 // [n_lev][2K][2K], carried filter state [64][2K + 1] and the per-wave
 // coefficient sums [nw][5K], all FP64.
-size_t adj_lds_bytes(int K, int nw, int n_lev) {
-  const int NS = 2 * K, NSP = NS + 1;
-  return ((size_t)nw * kWave * (NSP + 2) + (size_t)n_lev * NS * NS + (size_t)kWave * NSP +
-          (size_t)nw * 5 * K) *
-         sizeof(double);
+constexpr size_t adj_lds_doubles(int K, int nw, int n_lev) {
+  return (size_t)nw * kWave * (2 * K + 3) + (size_t)n_lev * 4 * K * K + (size_t)kWave * (2 * K + 1) +
+         (size_t)nw * 5 * K;
 }
+
+size_t adj_lds_bytes(int K, int nw, int n_lev) { return adj_lds_doubles(K, nw, n_lev) * sizeof(double); }
 
 namespace {
 
@@ -147,23 +147,81 @@ __device__ __forceinline__ double wave_sum_halving(const double (&gc)[NC]) {
 // FULL: the window fills every block (n_t = NB L), so no row is past its
 // end and the row loops run without a per-row validity branch (which costs
 // the exec-mask updates and the register copies at every join).
+// x rows of one window into this wave's slice of the LDS prefetch buffer
+// (row j of the wave's lanes at dst[j][lane]): buffer loads with an LDS
+// destination, so they need no registers and complete while the current
+// window is processed.  Out-of-range lanes receive zeros.
+template <int L>
+__device__ __forceinline__ void xpre_issue(float (*dst)[kWave], __amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t rb) {
+#pragma unroll
+  for (int j = 0; j < L; ++j)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)dst[j], 4,
+                                             vo + (uint32_t)j * rb, 0, 0, 0);
+}
+
 // RC: 0 stores the section outputs, 1 rebuilds them (every section of
 // second order), 2 rebuilds them with first-order sections among them (a
 // per-section test on the host's mask).
-template <int K, int L, bool UNIT, int RC, bool FULL>
+// MULTI: the launch takes p->n_win full windows, last to first.  The group
+// keeps its channels from window to window, so the adjoint state handed
+// from a window to the one before it stays in LDS and the coefficient sums
+// in a register; x of the window before is prefetched into LDS while a
+// window runs.  Same arithmetic, in the same order, as one launch per window.
+template <int K, int L, bool UNIT, int RC, bool FULL, bool MULTI>
 __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(3))) adj_kernel(AdjParams) {
   constexpr bool RECON = RC != 0;
   constexpr int NS = 2 * K, NSP = NS + 1, NC = 5 * K;
   constexpr bool kSgprLevels = K <= 4;
-  extern __shared__ double lds[];
+  // several windows per launch (MULTI): x prefetch buffer, the adjoint state
+  // between windows.  That kernel's LDS is all static (fixed tile), so the
+  // compiler can tell the exchanges apart from the prefetch buffer and waits
+  // for the prefetch only where the buffer is read.
+  extern __shared__ double lds_dyn[];
+  __shared__ double lds_fix[MULTI ? adj_lds_doubles(K, kMultiWaves, kMultiLevels) : 1];
+  __shared__ float xpre[MULTI ? kMultiWaves : 1][MULTI ? L : 1][kWave];
+  __shared__ double hand[MULTI ? kMultiGroup : 1][NS + 2];
+  double *const lds = MULTI ? lds_fix : lds_dyn;
+  if (group_of(aparams()->per_xcd) >= aparams()->n_grp) return;  // whole workgroup, before any barrier
+  const int n_win = MULTI ? aparams()->n_win : 1;
+  double gacc = 0.0;  // MULTI: the group's coefficient sums so far (threads < 5K)
+  if constexpr (MULTI) {
+    aparams_t p = aparams();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = uniform(threadIdx.x / kWave);
+    const int cwl = kMultiCwLog2;
+    const int64_t n_ch = p->n_ch;
+    const int64_t c = (int64_t)group_of(p->per_xcd) * (1 << cwl) + (lane & ((1 << cwl) - 1));
+    const int64_t row0 = (int64_t)(w * (kWave >> cwl) + (lane >> cwl)) * L;
+    const uint32_t vo = c < n_ch ? (uint32_t)((row0 * n_ch + c) * 4) : kOffInvalid;
+    if (threadIdx.x < NC) gacc = p->gpart[(size_t)group_of(p->per_xcd) * NC + threadIdx.x];
+    // the adjoint state handed in after the launch's last window goes to
+    // LDS with the rest: no window then waits on a global load issued after
+    // its prefetch (vector loads complete in order)
+    if (w == 0 && lane < (1 << cwl) && c < n_ch) {
+#pragma unroll
+      for (int i = 0; i < NS + 2; ++i) hand[lane][i] = p->adj[i * n_ch + c];
+    }
+    xpre_issue<L>(xpre[w], rsrc(p->x + (size_t)(n_win - 1) * p->win_elems, p->range), vo,
+                  fresh((uint32_t)n_ch * 4u));
+  }
+
+  for (int wi = n_win - 1; wi >= 0; --wi) {
+  // Everything per thread is derived afresh in each window from an opaque
+  // copy of the thread index, so that nothing (masks, addresses) is hoisted
+  // out of the window loop and held in registers across it.
+  uint32_t tid = threadIdx.x;
+  if constexpr (MULTI) asm volatile("" : "+v"(tid));
   aparams_t p = aparams();
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = uniform(threadIdx.x / kWave);
-  const int NW = p->nw;
-  const int cwl = p->cw_log2;
+  const int lane = tid & (kWave - 1);
+  const int w = uniform(tid / kWave);
+  // the several-window kernel has the geometry as constants: LDS addresses
+  // are then constant offsets of one array, which the compiler's alias
+  // analysis follows (it stops after a few chained offsets)
+  const int NW = MULTI ? kMultiWaves : p->nw;
+  const int cwl = MULTI ? kMultiCwLog2 : p->cw_log2;
+  const int n_lev = MULTI ? kMultiLevels : p->n_lev;
   const int CW = 1 << cwl, R = kWave >> cwl, NB = NW * R;
   const int g = group_of(p->per_xcd);
-  if (g >= p->n_grp) return;  // whole workgroup, before any barrier
   const int r = lane >> cwl, cl = lane & (CW - 1);
   const int b = w * R + r;
   const int my = w * kWave + lane;
@@ -173,16 +231,12 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
   double *xsl = lds;                       // [NW * 64][2]
   double *xch = xsl + 2 * NW * kWave;      // [NW * 64][NSP]
   double *pw = xch + NW * kWave * NSP;     // [n_lev][NS][NS]
-  double *zc = pw + p->n_lev * NS * NS;    // [CW][NSP]
+  double *zc = pw + n_lev * NS * NS;       // [CW][NSP]
   double *wsum = zc + kWave * NSP;         // [NW][NC]
   double *xme = xch + my * NSP;
-  {
-    const int n = p->n_lev * NS * NS;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) pw[k] = p->Pw[k];
-    if (b == 0) {
-#pragma unroll
-      for (int i = 0; i < NS; ++i) zc[cl * NSP + i] = cval ? p->zs0[i * n_ch + c] : 0.0;
-    }
+  if (wi == n_win - 1) {
+    const int n = n_lev * NS * NS;
+    for (int k = tid; k < n; k += blockDim.x) pw[k] = p->Pw[k];
   }
   const int n_t = p->n_t;
   const int b_end = (n_t - 1) / L;  // block holding the window's last row
@@ -191,8 +245,65 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
   const uint32_t rowb = (uint32_t)n_ch * 4u;
   const uint32_t vo = cval ? (uint32_t)((row0 * n_ch + c) * 4) : kOffInvalid;
 
+  // offsets of this window's rows and start-state slot (0 for one window)
+  const size_t xoff = MULTI ? (size_t)wi * (size_t)p->win_elems : 0;
+  const size_t ckoff = MULTI ? (size_t)wi * (size_t)p->ck_stride : 0;
+  // the adjoint state after the window (MULTI: in LDS, put there by the
+  // window after it or, for the launch's last window, by the prologue)
+  auto adj_in = [&](int i) -> double {
+    if constexpr (MULTI)
+      return hand[cl][i];
+    else
+      return aparams()->adj[i * n_ch + c];
+  };
+  if (b == 0) {
+    const double *zs0 = aparams()->zs0 + ckoff;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) zc[cl * NSP + i] = cval ? zs0[i * n_ch + c] : 0.0;
+  }
+
+  // MULTI: the STA/LTA start values are loaded before the prefetch is
+  // issued (vector loads complete in order, so a wait for a later load would
+  // wait for the prefetch as well)
+  int64_t g0 = 0;
+  double sl_s = 0.0, sl_l = 0.0;
+  if constexpr (MULTI) {
+    if (cval) {
+      const double *sl0 = aparams()->sl0 + ckoff;
+      g0 = reinterpret_cast<const int64_t *>(reinterpret_cast<const double *>(aparams()->cnt0) + ckoff)[c];
+      if (b == 0) {
+        sl_s = sl0[c];
+        sl_l = sl0[n_ch + c];
+      }
+    }
+  }
+
   float xv[L], gv[L];
-  {
+  if constexpr (MULTI) {
+    // this window's x is in LDS once its loads are done; the target rows
+    // load into registers, and once the LDS reads are done the window
+    // before starts loading into the same buffer
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+      const float t = xpre[w][j][lane];
+      xv[j] = cval ? t : 0.0f;
+    }
+    const __amdgpu_buffer_rsrc_t rg = rsrc(aparams()->g + xoff, aparams()->range);
+    const uint32_t rb = fresh(rowb);
+#pragma unroll
+    for (int j = 0; j < L; ++j) gv[j] = buf_ld(rg, vo + (uint32_t)j * rb);
+    __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+    // issued in every window (an empty range after the first window of the
+    // record reads zeros and moves nothing), so the compiler's count of the
+    // loads in flight is the same on every path and waits for the target
+    // rows do not wait for the prefetch
+    {
+      const bool more = wi > 0;
+      aparams_t q = aparams();
+      xpre_issue<L>(xpre[w], rsrc(more ? q->x + xoff - (size_t)q->win_elems : q->x, more ? q->range : 0), vo, rb);
+    }
+  } else {
     const __amdgpu_buffer_rsrc_t rx = rsrc(aparams()->x, aparams()->range);
     const __amdgpu_buffer_rsrc_t rg = rsrc(aparams()->g, aparams()->range);
     const uint32_t rb = fresh(rowb);
@@ -245,7 +356,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
     lds_barrier();
     double z[NS];
     {
-      const double *src = b == 0 ? zc + cl * NSP : xme - CW * NSP;
+      // one address from an index (a select of two pointers hides the array)
+      const double *src = lds + (b == 0 ? (int)(zc - lds) + cl * NSP : (int)(xme - lds) - CW * NSP);
 #pragma unroll
       for (int i = 0; i < NS; ++i) z[i] = src[i];
     }
@@ -294,16 +406,23 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
   };
 
   // ---------------- forward recompute: STA/LTA sums at block starts ----------------
-  int64_t g0 = 0;
   double Sin, Lin;  // scaled sums before the block's first row
   {
     aparams_t q = aparams();
     double S0 = 0.0, L0 = 0.0;
     if (cval) {
-      g0 = q->cnt0[c];
-      if (b == 0) {
-        S0 = q->sl0[c] / q->cs;
-        L0 = q->sl0[n_ch + c] / q->cl;
+      if constexpr (MULTI) {
+        if (b == 0) {
+          S0 = sl_s / q->cs;
+          L0 = sl_l / q->cl;
+        }
+      } else {
+        const double *sl0 = q->sl0;
+        g0 = q->cnt0[c];
+        if (b == 0) {
+          S0 = sl0[c] / q->cs;
+          L0 = sl0[n_ch + c] / q->cl;
+        }
       }
     }
     cdouble *dp = as_const(q->dpow);
@@ -359,8 +478,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
     const SlBack sb{q->cs, q->cl, q->asd, q->ald};
     double A = 0.0, B = 0.0;
     if (b == b_end && cval) {
-      A = q->adj[NS * n_ch + c];
-      B = q->adj[(NS + 1) * n_ch + c];
+      A = adj_in(NS);
+      B = adj_in(NS + 1);
     }
     // from the block end to its start, from zero (or the handed-in state)
 #pragma unroll
@@ -390,8 +509,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
       Ax = xsl[2 * (my + CW)];
       Bx = xsl[2 * (my + CW) + 1];
     } else if (b == b_end && cval) {
-      Ax = q->adj[NS * n_ch + c];
-      Bx = q->adj[(NS + 1) * n_ch + c];
+      Ax = adj_in(NS);
+      Bx = adj_in(NS + 1);
     }
     lds_barrier();
 #pragma unroll
@@ -414,7 +533,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
     cdouble *coef = as_const(q->coef);
     double u[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) u[i] = (b == b_end && cval) ? q->adj[i * n_ch + c] : 0.0;
+    for (int i = 0; i < NS; ++i) u[i] = (b == b_end && cval) ? adj_in(i) : 0.0;
     // local pass: delay-pair adjoints at the block start (the table holds
     // -a1, -a2, so ys is ybar - a1 u1 - a2 u2)
 #pragma unroll
@@ -462,7 +581,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
       for (int i = 0; i < NS; ++i) u[i] = src[i];
     } else {
 #pragma unroll
-      for (int i = 0; i < NS; ++i) u[i] = (b == b_end && cval) ? q->adj[i * n_ch + c] : 0.0;
+      for (int i = 0; i < NS; ++i) u[i] = (b == b_end && cval) ? adj_in(i) : 0.0;
     }
     lds_barrier();  // the adjoint state is overwritten below
 
@@ -470,7 +589,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
     double gc[NC];
 #pragma unroll
     for (int i = 0; i < NC; ++i) gc[i] = 0.0;
-    const __amdgpu_buffer_rsrc_t rgx = rsrc(q->gx, q->range);
+    const __amdgpu_buffer_rsrc_t rgx = rsrc(q->gx + xoff, q->range);
     const uint32_t rb = fresh(rowb);
     double zr[RECON ? NS : 1];  // rebuilding variant: forward state after the current row
     if constexpr (RECON) {
@@ -537,11 +656,18 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
       __builtin_amdgcn_sched_barrier(0);
     }
     if (b == 0 && cval) {  // the adjoint state before the window
-      double *adj = q->adj;
+      if (MULTI && wi > 0) {
 #pragma unroll
-      for (int i = 0; i < NS; ++i) adj[i * n_ch + c] = u[i];
-      adj[NS * n_ch + c] = xsl[2 * my];
-      adj[(NS + 1) * n_ch + c] = xsl[2 * my + 1];
+        for (int i = 0; i < NS; ++i) hand[cl][i] = u[i];
+        hand[cl][NS] = xsl[2 * my];
+        hand[cl][NS + 1] = xsl[2 * my + 1];
+      } else {
+        double *adj = q->adj;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) adj[i * n_ch + c] = u[i];
+        adj[NS * n_ch + c] = xsl[2 * my];
+        adj[(NS + 1) * n_ch + c] = xsl[2 * my + 1];
+      }
     }
 
     // coefficient gradients: over the wave (recursive halving up to 32
@@ -562,9 +688,20 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves
     if (threadIdx.x < NC) {
       double s = 0.0;
       for (int v = 0; v < NW; ++v) s += wsum[v * NC + threadIdx.x];
-      double *gp = aparams()->gpart + (size_t)g * NC + threadIdx.x;
-      *gp += s;
+      if constexpr (MULTI) {
+        gacc += s;
+      } else {
+        double *gp = aparams()->gpart + (size_t)g * NC + threadIdx.x;
+        *gp += s;
+      }
     }
+  }
+  }  // windows
+  if constexpr (MULTI) {
+    if (threadIdx.x < NC) aparams()->gpart[(size_t)group_of(aparams()->per_xcd) * NC + threadIdx.x] = gacc;
+    // the last window's (empty) prefetch is complete before the workgroup's
+    // LDS is released
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
   }
 }
 
@@ -572,14 +709,20 @@ template <int K, int L, bool U, int RC>
 hipError_t launch_u(const AdjParams &p, hipStream_t stream) {
   const size_t lds = adj_lds_bytes(K, p.nw, p.n_lev);
   const dim3 grid((unsigned)grid_for(p.per_xcd)), block((unsigned)(p.nw * kWave));
-  if constexpr (L == 16 && U && RC == 1) {  // the full-window variant for the default Butterworth path
-    const int nb = p.nw * (kWave >> p.cw_log2);
+  const int nb = p.nw * (kWave >> p.cw_log2);
+  if constexpr (L == 16 && U && RC == 1) {  // the full-window variants for the default Butterworth path
     if (p.n_t == nb * L) {
-      hipLaunchKernelGGL((adj_kernel<K, L, U, RC, true>), grid, block, lds, stream, p);
+      if (p.n_win > 1) {
+        if (!adj_multi_fits(p.nw, 1 << p.cw_log2, L, p.n_lev)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((adj_kernel<K, L, U, RC, true, true>), grid, block, 0, stream, p);
+      } else {
+        hipLaunchKernelGGL((adj_kernel<K, L, U, RC, true, false>), grid, block, lds, stream, p);
+      }
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((adj_kernel<K, L, U, RC, false>), grid, block, lds, stream, p);
+  if (p.n_win > 1) return hipErrorInvalidValue;  // several windows: full windows of the default path only
+  hipLaunchKernelGGL((adj_kernel<K, L, U, RC, false, false>), grid, block, lds, stream, p);
   return hipGetLastError();
 }
 

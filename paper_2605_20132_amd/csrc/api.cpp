@@ -210,6 +210,7 @@ struct filark_sos_state {
   size_t ff_bytes = 0;
   double *d_gpart = nullptr;
   size_t gpart_bytes = 0;
+  int adj_windows = 0;  // most adjoint windows per launch (0: no limit)
 };
 
 struct filark_stalta_state {
@@ -885,6 +886,13 @@ filark_status filark_tile_get(const void *obj, int kind, int *block, int *waves,
   return FILARK_OK;
 }
 
+filark_status filark_adjoint_windows_set(filark_sos_t sos, int max_windows) {
+  if (!sos) return fail(FILARK_EINVAL, "null state");
+  if (max_windows < 0) return fail(FILARK_EINVAL, "max_windows must be >= 0, got %d", max_windows);
+  sos->adj_windows = max_windows;
+  return FILARK_OK;
+}
+
 filark_status filark_state_bytes(const void *obj, int kind, size_t *bytes) {
   if (!obj || !bytes) return fail(FILARK_EINVAL, "null pointer");
   if (kind == FILARK_STATE_SOS) {
@@ -1081,25 +1089,44 @@ filark_status adjoint_run(filark_sos_t sos, filark_stalta_t sl, const double *ta
   p.ald = 1.0 - p.cl;
   p.nlta = sl->nlta;
   const uint64_t rowb = (uint64_t)n_ch * 4u;
-  for (int64_t w = n_win - 1; w >= 0 && e == hipSuccess; --w) {
-    const int64_t t0 = w * rows, nt = std::min(rows, n_t - t0);
-    const size_t off = (size_t)t0 * (size_t)n_ch;
+  // Full windows run several to a launch where the tile and the cascade
+  // allow (the default adjoint tile on a Butterworth-shaped cascade): the
+  // adjoint state then passes between them on chip.  The window starts are
+  // addressed as evenly spaced slots, so on the checkpoint path slot 0 gets
+  // a copy of the objects' state.
+  const bool multi = adj_multi_fits(ta.waves, ta.group, ta.block, ta.levels()) && K >= 2 &&
+                     sos->cas.unit_tail() && p.recon == 1 && sos->adj_windows != 1;
+  const int64_t cap = sos->adj_windows > 0 ? sos->adj_windows : n_win;
+  if (multi && !tape && e == hipSuccess && n_win > 1) e = seed(0, 0);
+  p.win_elems = rows * n_ch;
+  p.ck_stride = (int64_t)ck_doubles;
+  for (int64_t w = n_win - 1; w >= 0 && e == hipSuccess;) {
+    const int64_t nt = std::min(rows, n_t - w * rows);
+    // windows w_lo .. w in this launch, last to first
+    const int64_t w_lo = (multi && nt == rows) ? std::max<int64_t>(0, w - cap + 1) : w;
+    const size_t off = (size_t)(w_lo * rows) * (size_t)n_ch;
     p.x = x + off;
     p.g = g + off;
     p.gx = gx + off;
     p.n_t = (int32_t)nt;
+    p.n_win = (int32_t)(w - w_lo + 1);
     p.range = (int32_t)((uint64_t)nt * rowb);
     if (tape) {
-      const double *slot = tape + (size_t)w * ck_doubles;
+      const double *slot = tape + (size_t)w_lo * ck_doubles;
       p.zs0 = slot;
       p.sl0 = slot + (size_t)(2 * K) * n_ch;
       p.cnt0 = reinterpret_cast<const int64_t *>(slot + (size_t)(2 * K + 2) * n_ch);
+    } else if (p.n_win > 1 || w_lo > 0) {
+      p.zs0 = ck_z(w_lo);
+      p.sl0 = ck_s(w_lo);
+      p.cnt0 = ck_c(w_lo);
     } else {
-      p.zs0 = w == 0 ? sos->d_state : ck_z(w);
-      p.sl0 = w == 0 ? sl->d_state : ck_s(w);
-      p.cnt0 = w == 0 ? sl->d_cnt : ck_c(w);
+      p.zs0 = sos->d_state;
+      p.sl0 = sl->d_state;
+      p.cnt0 = sl->d_cnt;
     }
     e = launch_adj(p, K, ta.block, sos->cas.unit_tail(), stream);
+    w = w_lo - 1;
   }
   if (e == hipSuccess) e = launch_adj_reduce(sos->d_gpart, n_grp, 5 * K, gsos, stream);
   if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);

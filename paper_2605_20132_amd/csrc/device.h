@@ -45,6 +45,11 @@ __device__ __forceinline__ const FILARK_CONST P *kparams() {
 // Offsets at or past `range` read zero and drop stores; lanes whose channel
 // is past n_ch use an offset of 2^31, which is always out of range.
 constexpr uint32_t kOffInvalid = 0x80000000u;
+// s_waitcnt immediate that waits for LDS / scalar-memory results only
+// (lgkmcnt 0; vmcnt and expcnt at their maxima)
+constexpr int kWaitLgkm0 = 0xc07f;
+// ... and for vector memory only (vmcnt 0; expcnt and lgkmcnt at their maxima)
+constexpr int kWaitVm0 = 0x0f70;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, int range) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, range, 0x00020000);
 }

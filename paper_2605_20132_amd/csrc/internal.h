@@ -87,7 +87,26 @@ struct AdjParams {
   double asd, ald;     // 1 - 1/nsta, 1 - 1/nlta
   double cs, cl;       // 1/nsta, 1/nlta
   int64_t nlta;
+  // several full windows in one launch (n_win > 1, default adjoint tile
+  // only): x, g, gx, zs0, sl0, cnt0 and `range` describe the launch's first
+  // window; window i is offset by i * win_elems elements of x, g, gx and by
+  // i * ck_stride doubles of the start-state slots (zs0, sl0, cnt0 alike)
+  int32_t n_win;
+  int64_t win_elems;
+  int64_t ck_stride;
 };
+
+// The several-window adjoint kernel runs the default adjoint tile only
+// (16-row blocks, 4 waves, 8 channels: 32 blocks, 5 scan levels), with all
+// of its LDS static: an x prefetch buffer of 4 x 16 x 64 floats and the
+// handed-over adjoint state of the group's 8 channels besides the exchanges.
+constexpr int kMultiWaves = 4;
+constexpr int kMultiGroup = 8;
+constexpr int kMultiCwLog2 = 3;
+constexpr int kMultiLevels = 5;
+inline bool adj_multi_fits(int nw, int cw, int L, int n_lev) {
+  return L == 16 && nw == kMultiWaves && cw == kMultiGroup && n_lev == kMultiLevels;
+}
 
 // Two-threshold trigger on cf (one window of a chunk).  Same work split as
 // FwdParams with 48-row blocks.  Carried per channel: open flag, start of the
