@@ -269,14 +269,16 @@ def fwd_adjoint_leg(F, torch, dev, steps: int, parity: bool):
            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": gbs / HBM_PEAK_GBS, "traffic": None,
                         "kernel": "whole step: fwd_kernel<K=4, 64-row blocks, stalta> per chunk writing the tape, "
-                                  "then per chunk (last first) adj_kernel per 512-row window",
+                                  "then per chunk (last first) adj_kernel on its partial last window and "
+                                  "adj_kernel on its five full 512-row windows in one launch",
                         "algorithmic_bytes_per_step": 20.0 * n,
                         "forward": {"ms": ms_f, "algorithmic_gbs": 8.0 * n / (ms_f / 1e3) / 1e9,
                                     "frac": 8.0 * n / (ms_f / 1e3) / 1e9 / HBM_PEAK_GBS},
                         "adjoint": {"ms": ms_a, "algorithmic_gbs": 12.0 * n / (ms_a / 1e3) / 1e9,
                                     "frac": 12.0 * n / (ms_a / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                    "kernel": "adj_kernel<4, 16, unit, rebuild> (60 launches per step) and "
-                                              "adj_reduce_kernel (10)",
+                                    "kernel": "adj_kernel<4, 16, unit, rebuild, full, several windows> (10 launches "
+                                              "of 5 windows per step), adj_kernel<4, 16, unit, rebuild> on the "
+                                              "partial windows (10) and adj_reduce_kernel (10)",
                                     "adj_kernel_traffic": adj_traffic()}},
            "checkpoint_path_ms_per_step": ms_ck, "graph_replay_ms_per_step": ms_graph}
     if parity:
