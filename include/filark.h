@@ -343,10 +343,12 @@ filark_status filark_sos_stalta_adjoint_tape(filark_sos_t sos, filark_stalta_t s
  *            (a launch after such a change fails with FILARK_EINVAL; bind
  *            refuses a state whose block or waves differ from the batch's).
  *            A bind drops the graph held by _capture.
- *   _launch  enqueues the bound work on `stream`: a reset kernel (queue
- *            counters, completion stamps) and one persistent kernel whose
- *            workgroups (as many as stay resident, at most the longest
- *            queue) take items until their XCD's queue is empty; or, after
+ *   _launch  enqueues the bound work on `stream`: one persistent kernel
+ *            whose workgroups (as many as stay resident, at most the longest
+ *            queue) take items until their XCD's queue is empty, the last
+ *            one to leave clearing the queue counters for the next launch
+ *            (a launch that did not complete leaves the batch unusable:
+ *            destroy it); or, after
  *            _capture, one launch of the captured graph.  It allocates
  *            nothing and does not synchronise; every launch advances each
  *            stream's state by its chunk, exactly like filark_sos_process
@@ -358,7 +360,8 @@ filark_status filark_sos_stalta_adjoint_tape(filark_sos_t sos, filark_stalta_t s
  *            own must capture again after a bind.
  *   _stamps  synchronises `stream` and copies n + 1 uint64 values: the
  *            completion time of each stream's last item and, last, the time
- *            the launch started, in ticks of the device's 100 MHz clock.
+ *            the launch started (its first item was taken), in ticks of the
+ *            device's 100 MHz clock; of the last completed launch.
  * SOS only (no STA/LTA).  Errors as elsewhere; FILARK_EINVAL if a stream's
  * tile does not fit the device or the state objects disagree.
  */

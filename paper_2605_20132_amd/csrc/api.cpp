@@ -233,7 +233,7 @@ struct filark_batch {
   size_t descs_bytes = 0;
   BatchItem *d_items = nullptr;
   size_t items_bytes = 0;
-  uint32_t *d_heads = nullptr;              // [8] queue counters
+  uint32_t *d_heads = nullptr;              // [8] queue counters, [1] workgroups done
   unsigned long long *d_stamps = nullptr;   // [n + 1]
   BatchParams bp{};
   int kmax = 0, grid = 0;
@@ -1221,8 +1221,8 @@ filark_status filark_batch_create(filark_batch_t *out, int n, const filark_sos_t
   if (prev_dev != b->device) HIP_TRY(hipSetDevice(b->device));
   hipError_t e = hipMalloc(&b->d_stamps, (size_t)(n + 1) * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMemsetAsync(b->d_stamps, 0, (size_t)(n + 1) * sizeof(unsigned long long), stream);
-  if (e == hipSuccess) e = hipMalloc(&b->d_heads, 8 * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMemsetAsync(b->d_heads, 0, 8 * sizeof(uint32_t), stream);
+  if (e == hipSuccess) e = hipMalloc(&b->d_heads, 9 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_heads, 0, 9 * sizeof(uint32_t), stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (prev_dev != b->device) (void)hipSetDevice(prev_dev);
@@ -1288,7 +1288,8 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
     // groups dealt to the XCDs in contiguous slabs, so the groups that share
     // cache lines meet in one L2
     const int per = per_xcd_for(n_grp);
-    for (int g = 0; g < n_grp; ++g) lists[g / per].push_back({desc0, n_win, K, g, s, {0, 0, 0}});
+    const int unit = st->cas.unit_tail() ? 1 : 0;
+    for (int g = 0; g < n_grp; ++g) lists[g / per].push_back({desc0, n_win, K, g, s, unit, {0, 0}});
   }
   // each queue longest items first (windows x sections): the last items to
   // start are the shortest

@@ -19,35 +19,41 @@ size_t fwd_lds_bytes(int K, int nw, int n_lev, int cw) {
 
 namespace {
 
-// Reset of a batched launch: the queue counters, the stream stamps, and the
-// start stamp in slot n (a kernel, so the reset replays correctly in a graph).
-__global__ void __launch_bounds__(256) batch_reset_kernel(uint32_t *heads, unsigned long long *stamps, int n) {
-  if (threadIdx.x < 8) heads[threadIdx.x] = 0u;
-  for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) stamps[i] = 0ull;
-  if (threadIdx.x == 0) stamps[n] = (unsigned long long)__builtin_amdgcn_s_memrealtime();
-}
-
 // One item: channel group g of one stream, its windows in order.  The state a
 // window's last-row lanes write is read by the next window's first-block
 // lanes, other waves of this workgroup: the release / acquire fences at
 // workgroup scope around the barrier order those global accesses (the
 // workgroup's waves share one L1).
-template <int K>
+template <int K, bool UNIT>
 __device__ __forceinline__ void batch_walk(const FILARK_CONST BatchParams *bp, const FILARK_CONST BatchItem *it) {
   const int desc0 = it->desc0, n_win = it->n_win, g = it->group;
   for (int w = 0; w < n_win; ++w) {
     const PSrc ps{(kparams_t)(bp->descs + desc0 + w)};
-    fwd_body<K, 48, false, true, false, false, false>(ps, g);
+    fwd_body<K, 48, false, true, UNIT, false, false>(ps, g);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
 }
 
+// An item with its cascade's section count and step.
+template <int K>
+__device__ __forceinline__ void batch_item(const FILARK_CONST BatchParams *bp, const FILARK_CONST BatchItem *it) {
+  if constexpr (K >= 2) {
+    if (it->unit) {
+      batch_walk<K, true>(bp, it);
+      return;
+    }
+  }
+  batch_walk<K, false>(bp, it);
+}
+
 // The persistent batched kernel for cascades of up to KMAX sections (the
 // registers are those of the largest cascade compiled in, so the host picks
 // the smallest KMAX that covers its streams).  Every workgroup leaves when
-// its XCD's queue is empty.
+// its XCD's queue is empty; the last one to leave clears the counters for
+// the next launch, so a launch is this one kernel (no reset kernel before
+// it, in a graph or not).
 template <int KMAX>
 __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_waves_per_eu(3)))
 fwd_batch_kernel(BatchParams) {
@@ -65,22 +71,37 @@ fwd_batch_kernel(BatchParams) {
   for (;;) {
     if (wave0) {
       const uint32_t old = atomicAdd(bp->heads + x, lane0 ? 1u : 0u);
-      next = q0 + (int)__builtin_amdgcn_readfirstlane((int)old);
+      const int taken = __builtin_amdgcn_readfirstlane((int)old);
+      next = q0 + taken;
+      // the launch's start: the first item of XCD 0's queue (every lane
+      // stores the same value)
+      if (x == 0 && taken == 0) bp->stamps[bp->n_streams] = __builtin_amdgcn_s_memrealtime();
     }
     __syncthreads();
     const int i = uniform(next);
     __syncthreads();  // every wave has read `next` before it is written again
-    if (i >= q1) break;  // the whole workgroup: i is uniform
+    if (i >= q1) {  // the whole workgroup: i is uniform
+      if (wave0) {
+        // workgroups leave once their last atomic on the queue counters is
+        // done, so the last one to leave finds no other still using them
+        const uint32_t done = atomicAdd(bp->heads + 8, lane0 ? 1u : 0u);
+        if (__builtin_amdgcn_readfirstlane((int)done) + 1 == (int)gridDim.x && lane0) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) atomicExch(bp->heads + k, 0u);
+        }
+      }
+      break;
+    }
     const FILARK_CONST BatchItem *it = (const FILARK_CONST BatchItem *)bp->items + i;
     switch (it->K) {
-      case 1: batch_walk<1>(bp, it); break;
-      case 2: if constexpr (KMAX >= 2) batch_walk<2>(bp, it); break;
-      case 3: if constexpr (KMAX >= 3) batch_walk<3>(bp, it); break;
-      case 4: if constexpr (KMAX >= 4) batch_walk<4>(bp, it); break;
-      case 5: if constexpr (KMAX >= 5) batch_walk<5>(bp, it); break;
-      case 6: if constexpr (KMAX >= 6) batch_walk<6>(bp, it); break;
-      case 7: if constexpr (KMAX >= 7) batch_walk<7>(bp, it); break;
-      case 8: if constexpr (KMAX >= 8) batch_walk<8>(bp, it); break;
+      case 1: batch_item<1>(bp, it); break;
+      case 2: if constexpr (KMAX >= 2) batch_item<2>(bp, it); break;
+      case 3: if constexpr (KMAX >= 3) batch_item<3>(bp, it); break;
+      case 4: if constexpr (KMAX >= 4) batch_item<4>(bp, it); break;
+      case 5: if constexpr (KMAX >= 5) batch_item<5>(bp, it); break;
+      case 6: if constexpr (KMAX >= 6) batch_item<6>(bp, it); break;
+      case 7: if constexpr (KMAX >= 7) batch_item<7>(bp, it); break;
+      case 8: if constexpr (KMAX >= 8) batch_item<8>(bp, it); break;
       default: break;
     }
     // batch_walk ends on a barrier: every wave's stores of the item are done
@@ -93,9 +114,6 @@ fwd_batch_kernel(BatchParams) {
 
 template <int KMAX>
 hipError_t launch_batch_k(const BatchParams &bp, int grid, int nw, size_t lds, hipStream_t stream) {
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, stream, bp.heads, bp.stamps, bp.n_streams);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((fwd_batch_kernel<KMAX>), dim3((unsigned)grid), dim3((unsigned)(nw * kWave)), lds, stream, bp);
   return hipGetLastError();
 }

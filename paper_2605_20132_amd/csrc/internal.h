@@ -159,13 +159,17 @@ struct BatchItem {
   int32_t K;       // sections
   int32_t group;   // channel group
   int32_t stream;
-  int32_t pad[3];
+  int32_t unit;    // 1: sections 2..K have b0 = b2 = 1 (the shorter section step)
+  int32_t pad[2];
 };
 struct BatchParams {
   const FwdParams *descs;
   const BatchItem *items;
-  uint32_t *heads;             // [8] queue counters, zeroed before each launch
-  unsigned long long *stamps;  // [n_streams + 1]: completion stamps, then the start stamp
+  uint32_t *heads;             // [8] queue counters, then [1] workgroups done; the last
+                               // workgroup to leave sets all 9 back to 0 for the next launch
+  unsigned long long *stamps;  // [n_streams + 1]: completion stamps (raised with atomic max,
+                               // so a launch's stamps exceed every earlier one's), then the
+                               // start stamp (the first item taken from XCD 0's queue)
   int32_t qoff[9];
   int32_t n_streams;
 };

@@ -75,6 +75,14 @@ def test_batch_equals_per_stream_calls_and_oracle(F):
     st_ = b.stamps()
     start, ends = int(st_[-1]), st_[:-1].astype(np.int64)
     assert np.all(ends > start)
+    # a second launch (the queue counters cleared themselves at the end of the
+    # first): its start follows every completion of the first, and its own
+    # completions follow its start
+    b.launch()
+    st2 = b.stamps()
+    start2, ends2 = int(st2[-1]), st2[:-1].astype(np.int64)
+    assert start2 > int(ends.max())
+    assert np.all(ends2 > start2)
 
 
 def test_batch_carries_state_over_chunks(F):
