@@ -1288,8 +1288,7 @@ filark_status filark_batch_bind(filark_batch_t b, const float *const *in, float 
     // groups dealt to the XCDs in contiguous slabs, so the groups that share
     // cache lines meet in one L2
     const int per = per_xcd_for(n_grp);
-    const int unit = st->cas.unit_tail() ? 1 : 0;
-    for (int g = 0; g < n_grp; ++g) lists[g / per].push_back({desc0, n_win, K, g, s, unit, {0, 0}});
+    for (int g = 0; g < n_grp; ++g) lists[g / per].push_back({desc0, n_win, K, g, s, {0, 0, 0}});
   }
   // each queue longest items first (windows x sections): the last items to
   // start are the shortest

@@ -24,28 +24,16 @@ namespace {
 // lanes, other waves of this workgroup: the release / acquire fences at
 // workgroup scope around the barrier order those global accesses (the
 // workgroup's waves share one L1).
-template <int K, bool UNIT>
+template <int K>
 __device__ __forceinline__ void batch_walk(const FILARK_CONST BatchParams *bp, const FILARK_CONST BatchItem *it) {
   const int desc0 = it->desc0, n_win = it->n_win, g = it->group;
   for (int w = 0; w < n_win; ++w) {
     const PSrc ps{(kparams_t)(bp->descs + desc0 + w)};
-    fwd_body<K, 48, false, true, UNIT, false, false>(ps, g);
+    fwd_body<K, 48, false, true, false, false, false>(ps, g);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
   }
-}
-
-// An item with its cascade's section count and step.
-template <int K>
-__device__ __forceinline__ void batch_item(const FILARK_CONST BatchParams *bp, const FILARK_CONST BatchItem *it) {
-  if constexpr (K >= 2) {
-    if (it->unit) {
-      batch_walk<K, true>(bp, it);
-      return;
-    }
-  }
-  batch_walk<K, false>(bp, it);
 }
 
 // The persistent batched kernel for cascades of up to KMAX sections (the
@@ -94,14 +82,14 @@ fwd_batch_kernel(BatchParams) {
     }
     const FILARK_CONST BatchItem *it = (const FILARK_CONST BatchItem *)bp->items + i;
     switch (it->K) {
-      case 1: batch_item<1>(bp, it); break;
-      case 2: if constexpr (KMAX >= 2) batch_item<2>(bp, it); break;
-      case 3: if constexpr (KMAX >= 3) batch_item<3>(bp, it); break;
-      case 4: if constexpr (KMAX >= 4) batch_item<4>(bp, it); break;
-      case 5: if constexpr (KMAX >= 5) batch_item<5>(bp, it); break;
-      case 6: if constexpr (KMAX >= 6) batch_item<6>(bp, it); break;
-      case 7: if constexpr (KMAX >= 7) batch_item<7>(bp, it); break;
-      case 8: if constexpr (KMAX >= 8) batch_item<8>(bp, it); break;
+      case 1: batch_walk<1>(bp, it); break;
+      case 2: if constexpr (KMAX >= 2) batch_walk<2>(bp, it); break;
+      case 3: if constexpr (KMAX >= 3) batch_walk<3>(bp, it); break;
+      case 4: if constexpr (KMAX >= 4) batch_walk<4>(bp, it); break;
+      case 5: if constexpr (KMAX >= 5) batch_walk<5>(bp, it); break;
+      case 6: if constexpr (KMAX >= 6) batch_walk<6>(bp, it); break;
+      case 7: if constexpr (KMAX >= 7) batch_walk<7>(bp, it); break;
+      case 8: if constexpr (KMAX >= 8) batch_walk<8>(bp, it); break;
       default: break;
     }
     // batch_walk ends on a barrier: every wave's stores of the item are done

@@ -159,8 +159,7 @@ struct BatchItem {
   int32_t K;       // sections
   int32_t group;   // channel group
   int32_t stream;
-  int32_t unit;    // 1: sections 2..K have b0 = b2 = 1 (the shorter section step)
-  int32_t pad[2];
+  int32_t pad[3];
 };
 struct BatchParams {
   const FwdParams *descs;
