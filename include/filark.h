@@ -492,6 +492,25 @@ filark_status filark_trigger_state_set(filark_trigger_t st, const int64_t *open_
 filark_status filark_trigger_destroy(filark_trigger_t st);
 
 /*
+ * The monitor chain in one pass over a chunk (the energy-detector monitor of
+ * Section 3.4): SOS cascade, STA/LTA characteristic and two-threshold
+ * trigger, each with its carried state.  The same outputs, states and events
+ * as filark_sos_stalta_process followed by filark_trigger_process on its cf
+ * (events as a set: their order in the list depends on timing in either
+ * case), without cf going through memory unless asked for.
+ *   in          device FP32 [n_t][n_ch].
+ *   y_or_null   device FP32 [n_t][n_ch] or NULL (not written).
+ *   cf_or_null  device FP32 [n_t][n_ch] or NULL (not written).
+ *   events, cap, count  as filark_trigger_process.
+ * The states' forward tile must have 48-row blocks (the default).
+ * Asynchronous on `stream`.  Errors: FILARK_EINVAL, FILARK_ESHAPE,
+ * FILARK_EHIP.
+ */
+filark_status filark_monitor_process(filark_sos_t sos, filark_stalta_t sl, filark_trigger_t tr, const float *in,
+                                     float *y_or_null, float *cf_or_null, int64_t *events, int64_t cap,
+                                     uint64_t *count, int64_t n_ch, int64_t n_t, hipStream_t stream);
+
+/*
  * Synchronise `stream` and report an asynchronous HIP error of the work
  * enqueued on it (FILARK_EHIP).  kind as above.
  */

@@ -35,7 +35,7 @@ EXPORTS = (
     "filark_state_load", "filark_sos_stalta_adjoint", "filark_adjoint_tape_bytes",
     "filark_sos_stalta_process_tape", "filark_sos_stalta_adjoint_tape", "filark_batch_create", "filark_batch_bind",
     "filark_batch_launch", "filark_batch_capture", "filark_autotune", "filark_batch_stamps", "filark_batch_destroy", "filark_trigger_init",
-    "filark_trigger_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
+    "filark_trigger_process", "filark_monitor_process", "filark_trigger_state_get", "filark_trigger_state_set", "filark_trigger_destroy",
     "filark_sos_filtfilt", "filark_sos_filtfilt_noalloc", "filark_ema_init", "filark_ema_process", "filark_ema_state_get", "filark_ema_state_set",
     "filark_ema_destroy", "filark_fir_init", "filark_fir_set_tile", "filark_fir_set_method", "filark_fir_process", "filark_fir_state_get",
     "filark_fir_state_set", "filark_fir_destroy",
@@ -99,6 +99,7 @@ def lib():
     I64P = ctypes.POINTER(i64)
     L.filark_trigger_init.argtypes = [ctypes.POINTER(vp), ctypes.c_float, ctypes.c_float, i64, vp]
     L.filark_trigger_process.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp]
+    L.filark_monitor_process.argtypes = [vp, vp, vp, vp, vp, vp, vp, i64, vp, i64, i64, vp]
     L.filark_trigger_state_get.argtypes = [vp, I64P, I64P, vp]
     L.filark_trigger_state_set.argtypes = [vp, I64P, i64, vp]
     L.filark_trigger_destroy.argtypes = [vp]
@@ -530,6 +531,27 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def monitor_process(sos: SOSState, sl: StaLtaState, trig: "Trigger", x, events, count, y=None, cf=None,
+                    stream=None):
+    """The monitor chain in one pass (filark_monitor_process): x float32 CUDA
+    [n_t, n_ch] through the cascade, the STA/LTA and the trigger; events int64
+    CUDA [cap, 3] and count (one 64-bit CUDA element) as Trigger.process; y and
+    cf (float32 CUDA [n_t, n_ch]) are written only when given.  Asynchronous."""
+    import torch
+
+    n_t, n_ch = x.shape
+    if not (isinstance(events, torch.Tensor) and events.is_cuda and events.dtype == torch.int64
+            and events.dim() == 2 and events.shape[1] == 3 and events.is_contiguous()):
+        raise FilarkError(EINVAL, "events must be a contiguous int64 CUDA tensor [cap, 3]")
+    if not (isinstance(count, torch.Tensor) and count.is_cuda and count.numel() == 1 and count.element_size() == 8):
+        raise FilarkError(EINVAL, "count must be a one-element 64-bit CUDA tensor")
+    yp = _dev_f32(y, "y") if y is not None else ctypes.c_void_p(0)
+    cp = _dev_f32(cf, "cf") if cf is not None else ctypes.c_void_p(0)
+    _check(lib().filark_monitor_process(sos.handle, sl.handle, trig._h, _dev_f32(x, "x"), yp, cp,
+                                        ctypes.c_void_p(events.data_ptr()), events.shape[0],
+                                        ctypes.c_void_p(count.data_ptr()), n_ch, n_t, _stream(stream)))
 
 
 class Trigger:

@@ -17,8 +17,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libfilark.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["fwd_l48.hip", "fwd_l64.hip", "fwd_l32.hip", "fwd.hip", "adj.hip", "api.cpp", "design.cpp", "trig.hip",
-           "ema.hip", "fir.hip", "fft.hip"]
+SOURCES = ["fwd_l48.hip", "fwd_l64.hip", "fwd_l32.hip", "fwd.hip", "monitor.hip", "adj.hip", "api.cpp",
+           "design.cpp", "trig.hip", "ema.hip", "fir.hip", "fft.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -400,13 +400,10 @@ int64_t launch_rows(const Tile &t, int64_t n_ch) {
 // Forward launches over n_t rows from `in`, one window each, with the state
 // at (zs, sl, cnt) updated in place.  y / cf may be null; with neither (and
 // `states_only`) nothing but the state is written.
-hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_state *sl, const Tile &t,
-                            double *zs, double *slst, int64_t *cnt, const float *in, float *y, float *cf,
-                            bool states_only, int64_t n_ch, int64_t n_t, hipStream_t stream,
-                            bool rev = false, const CkSpec *ck = nullptr, bool ckp_tables = false) {
-  const uint64_t rowb = (uint64_t)n_ch * 4u;
-  const int64_t rows = launch_rows(t, n_ch);
-  const int K = sos ? sos->cas.K : 0;
+// Parameters common to every window of a forward launch sequence (pointers
+// and the window's row count are set per window).
+FwdParams fwd_base(const filark_sos_state *sos, const filark_stalta_state *sl, const Tile &t, double *zs,
+                   double *slst, int64_t *cnt, int64_t n_ch, bool ckp_tables) {
   FwdParams p;
   std::memset(&p, 0, sizeof p);
   p.n_ch = n_ch;
@@ -437,6 +434,17 @@ hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_sta
     p.al = (float)p.ald;
     p.kappa = (float)((double)sl->nlta / (double)sl->nsta);
   }
+  return p;
+}
+
+hipError_t forward_launches(const filark_sos_state *sos, const filark_stalta_state *sl, const Tile &t,
+                            double *zs, double *slst, int64_t *cnt, const float *in, float *y, float *cf,
+                            bool states_only, int64_t n_ch, int64_t n_t, hipStream_t stream,
+                            bool rev = false, const CkSpec *ck = nullptr, bool ckp_tables = false) {
+  const uint64_t rowb = (uint64_t)n_ch * 4u;
+  const int64_t rows = launch_rows(t, n_ch);
+  const int K = sos ? sos->cas.K : 0;
+  FwdParams p = fwd_base(sos, sl, t, zs, slst, cnt, n_ch, ckp_tables);
   hipError_t e = hipSuccess;
   // time-reversed: the windows last to first, each one's rows last to first
   const int64_t n_win = (n_t + rows - 1) / rows;
@@ -1730,6 +1738,66 @@ filark_status filark_trigger_process(filark_trigger_t st, const float *cf, int64
   }
   if (prev_dev != st->device) (void)hipSetDevice(prev_dev);
   if (e != hipSuccess) return fail(FILARK_EHIP, "trigger launch failed: %s", hipGetErrorString(e));
+  return FILARK_OK;
+}
+
+filark_status filark_monitor_process(filark_sos_t sos, filark_stalta_t sl, filark_trigger_t tr, const float *in,
+                                     float *y_or_null, float *cf_or_null, int64_t *events, int64_t cap,
+                                     uint64_t *count, int64_t n_ch, int64_t n_t, hipStream_t stream) {
+  if (!sos || !sl || !tr) return fail(FILARK_EINVAL, "null state");
+  if (sos->device != sl->device || sos->device != tr->device)
+    return fail(FILARK_EINVAL, "states live on different devices");
+  if (sos->n_ch != n_ch || sl->n_ch != n_ch || tr->n_ch != n_ch)
+    return fail(FILARK_ESHAPE, "n_ch %lld differs from a state's", (long long)n_ch);
+  if (n_t < 0 || cap < 0) return fail(FILARK_EINVAL, "negative n_t or capacity");
+  if (!count || (cap > 0 && !events)) return fail(FILARK_EINVAL, "null count or events pointer");
+  if (n_t == 0) return FILARK_OK;
+  if (!in) return fail(FILARK_EINVAL, "null input pointer");
+  if (y_or_null && cf_or_null && (const void *)y_or_null == (const void *)cf_or_null)
+    return fail(FILARK_EINVAL, "y and cf must differ");
+  const Tile t = sos->fwd.tile;
+  if (!(sl->fwd.tile == t)) return fail(FILARK_EINVAL, "tile shapes of the states differ (set both with filark_tile_set)");
+  if (t.block != 48) return fail(FILARK_EINVAL, "the monitor runs 48-row blocks (tile block %d)", t.block);
+  const int64_t rows = launch_rows(t, n_ch);
+  if (rows == 0) return fail(FILARK_EINVAL, "n_ch %lld too large", (long long)n_ch);
+  const int K = sos->cas.K;
+  filark_status rc = check_lds(fwd_lds_bytes(K, t.waves, t.levels(), t.group), t, K, sos->device);
+  if (rc != FILARK_OK) return rc;
+  const int prev_dev = current_device();
+  if (prev_dev != sos->device) HIP_TRY(hipSetDevice(sos->device));
+  MonParams m;
+  std::memset(&m, 0, sizeof m);
+  m.f = fwd_base(sos, sl, t, sos->d_state, sl->d_state, sl->d_cnt, n_ch, false);
+  TrigParams &q = m.t;
+  q.n_ch = n_ch;
+  q.cw_log2 = m.f.cw_log2;
+  q.nw = m.f.nw;
+  q.n_grp = m.f.n_grp;
+  q.per_xcd = m.f.per_xcd;
+  q.on = tr->on;
+  q.off = tr->off;
+  q.open = tr->d_open;
+  q.t_on = tr->d_ton;
+  q.cnt = tr->d_cnt;
+  q.ev = events;
+  q.cap = cap;
+  q.count = reinterpret_cast<unsigned long long *>(count);
+  const uint64_t rowb = (uint64_t)n_ch * 4u;
+  hipError_t e = hipSuccess;
+  for (int64_t t0 = 0; t0 < n_t && e == hipSuccess; t0 += rows) {
+    const int64_t nt = std::min(rows, n_t - t0);
+    const size_t off = (size_t)t0 * (size_t)n_ch;
+    m.f.x = in + off;
+    m.f.y = y_or_null ? y_or_null + off : nullptr;
+    m.f.cf = cf_or_null ? cf_or_null + off : nullptr;
+    m.f.n_t = (int32_t)nt;
+    m.f.range = (int32_t)((uint64_t)nt * rowb);
+    m.f.out_range = m.f.range;
+    q.n_t = (int32_t)nt;
+    e = launch_monitor(m, K, y_or_null != nullptr, sos->cas.unit_tail(), stream);
+  }
+  if (prev_dev != sos->device) (void)hipSetDevice(prev_dev);
+  if (e != hipSuccess) return fail(FILARK_EHIP, "monitor launch failed: %s", hipGetErrorString(e));
   return FILARK_OK;
 }
 

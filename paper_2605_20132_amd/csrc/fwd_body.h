@@ -42,6 +42,7 @@
 #pragma once
 
 #include "device.h"
+#include "trig_body.h"
 
 namespace filark {
 
@@ -193,15 +194,16 @@ __device__ __forceinline__ void sums(PSrc ps, const float (&xv)[L], double &s_lo
 }
 
 // Pass B: the STA/LTA sums from their exact entry values and the
-// characteristic function, stored as produced.  Rows before the warm-up
-// boundary (block row < jwarm) give zero.
-template <int L, bool WARM, bool NT>
-__device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, float Lf, int jwarm,
+// characteristic function, stored as produced (not stored without a cf
+// buffer).  Rows before the warm-up boundary (block row < jwarm) give zero.
+// KEEP: cf replaces y in xv (for the trigger of the monitor launch).
+template <int L, bool WARM, bool NT, bool KEEP = false>
+__device__ __forceinline__ void passb(PSrc ps, float (&xv)[L], float Sf, float Lf, int jwarm,
                                       const Rows<false> &rw) {
   kparams_t p = ps.get();
   const float as = p->as, al = p->al, kappa = p->kappa;
-  const RowBuf rcb{(const char *)(p->cf ? (const void *)p->cf : (const void *)p->x), (uint32_t)p->out_range,
-                   fresh((uint32_t)p->n_ch * 4u)};
+  const RowBuf rcb{(const char *)(p->cf ? (const void *)p->cf : (const void *)p->x),
+                   p->cf ? (uint32_t)p->out_range : 0u, fresh((uint32_t)p->n_ch * 4u)};
 #pragma unroll
   for (int j = 0; j < L; ++j) {
     const float e = xv[j] * xv[j];
@@ -210,6 +212,7 @@ __device__ __forceinline__ void passb(PSrc ps, const float (&xv)[L], float Sf, f
     const float r = kappa * Sf * __builtin_amdgcn_rcpf(Lf);
     const float out = (Lf > 0.0f && (!WARM || j >= jwarm)) ? r : 0.0f;
     buf_st<NT>(rcb.at(j), rw.vo, out);
+    if constexpr (KEEP) xv[j] = out;
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -347,7 +350,9 @@ __device__ __forceinline__ void fwd_load(PSrc ps, int g, float (&xv)[L]) {
 
 // Everything after the loads for channel group g of the stream described by
 // ps, over one window of rows: carries, passes, stores, carried state.
-template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV, bool NT>
+// TRIG (monitor launch; ps points at a MonParams): the two-threshold trigger
+// then runs on the window's cf, kept in registers.
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV, bool NT, bool TRIG = false>
 __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
   constexpr int NS = 2 * K;
   extern __shared__ double lds[];
@@ -518,9 +523,11 @@ __device__ __forceinline__ void fwd_compute(PSrc ps, int g, float (&xv)[L]) {
     // past the warm-up for every row of the wave (a wave-uniform test): no
     // per-row comparison with the warm-up boundary
     if (g0 + (int64_t)w * R * L >= q->nlta)
-      passb<L, false, NT>(ps, xv, (float)Sin, (float)Lin, 0, Rows<false>(q, row0, c, cval));
+      passb<L, false, NT, TRIG>(ps, xv, (float)Sin, (float)Lin, 0, Rows<false>(q, row0, c, cval));
     else
-      passb<L, true, NT>(ps, xv, (float)Sin, (float)Lin, jwarm, Rows<false>(q, row0, c, cval));
+      passb<L, true, NT, TRIG>(ps, xv, (float)Sin, (float)Lin, jwarm, Rows<false>(q, row0, c, cval));
+    if constexpr (TRIG)
+      trigk::trig_window<L>(&reinterpret_cast<const FILARK_CONST MonParams *>(ps.get())->t, g, xv);
   }
 }
 
@@ -542,7 +549,7 @@ __device__ __forceinline__ void warm_g(PSrc ps) {
   }
 }
 
-template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV, bool NT>
+template <int K, int L, bool STALTA, bool WRITE_Y, bool UNIT, bool REV, bool NT, bool TRIG = false>
 __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   const FwdLds m(ps.get(), 2 * K);
   Staged<K, STALTA> sa;
@@ -554,7 +561,7 @@ __device__ __forceinline__ void fwd_body(PSrc ps, int g) {
   warm_g<K, L>(ps);
   sa.write(ps, m);
   tb.write(ps, m);
-  fwd_compute<K, L, STALTA, WRITE_Y, UNIT, REV, NT>(ps, g, xv);
+  fwd_compute<K, L, STALTA, WRITE_Y, UNIT, REV, NT, TRIG>(ps, g, xv);
 }
 
 // One channel group per workgroup.  At least three waves per SIMD for 48-

@@ -129,6 +129,15 @@ struct TrigParams {
 
 hipError_t launch_trig(const TrigParams &p, int L, hipStream_t stream);
 
+// The monitor launch: one window of the fused forward (SOS + STA/LTA, y and
+// cf optional) whose cf goes on in registers to the trigger; t describes the
+// same window and channel groups (t.cf and t.range unused).
+struct MonParams {
+  FwdParams f;
+  TrigParams t;
+};
+hipError_t launch_monitor(const MonParams &p, int K, bool write_y, bool unit, hipStream_t stream);
+
 // Stateful exponential-average operator (running-mean removal or running
 // AGC), one window of a chunk; same work split as FwdParams, 48-row blocks.
 struct EmaParams {
