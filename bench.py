@@ -633,7 +633,59 @@ def trigger_leg(F, torch, dev, steps: int, parity: bool):
         log(f"[bench] trigger parity on {len(cols)} channels: {len(o)} events, exact {exact}")
         t2.close()
     tr.close()
+    del cf
+    res["monitor"] = monitor_chain(F, torch, dev, steps, ev, count)
     return res
+
+
+def monitor_chain(F, torch, dev, steps: int, ev, count):
+    """The monitor chain on the plain-forward record (6000 ch x 90,000 in 60
+    chunks of 1500, BP order 8 + STA/LTA 0.2 / 2 s, thresholds 3.0 / 1.5):
+    x -> events as two calls per chunk (filark_sos_stalta_process writing cf,
+    filark_trigger_process reading it) and as one filark_monitor_process
+    launch per chunk (cf kept in registers, not written)."""
+    import synth
+
+    w = synth.make_config2(device=dev)
+    x = w.x
+    n_t, n_ch = x.shape
+    chunk, on, off = w.chunk, 3.0, 1.5
+    sos = F.sos_design(w.order, w.btype, w.f1, w.f2, w.fs)
+    nsta, nlta = round(w.sta_s * w.fs), round(w.lta_s * w.fs)
+    cf = torch.empty_like(x)
+    objs = [(F.SOSState(sos, n_ch), F.StaLtaState(float(nsta), float(nlta), 1.0, n_ch), F.Trigger(n_ch, on, off))
+            for _ in range(2)]
+
+    def two(o):
+        count.zero_()
+        for a in range(0, n_t, chunk):
+            F.sos_stalta_process(o[0], o[1], x[a:a + chunk], cf=cf[a:a + chunk], write_y=False)
+            o[2].process(cf[a:a + chunk], ev, count)
+
+    def one(o):
+        count.zero_()
+        for a in range(0, n_t, chunk):
+            F.monitor_process(o[0], o[1], o[2], x[a:a + chunk], ev, count)
+
+    out = {"workload": f"{n_ch} ch x {n_t} samples in chunks of {chunk}: BP order {w.order} + STA/LTA "
+                       f"{nsta}/{nlta} + trigger {on} / {off}, x read, events written"}
+    for name, fn, o in (("two_calls_ms_per_step", two, objs[0]), ("one_pass_ms_per_step", one, objs[1])):
+        fn(o)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn(o)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / steps
+        out["events_per_step"] = int(count.item())
+    log(f"[bench] monitor chain x -> events: two calls {out['two_calls_ms_per_step']:.3f} ms/step, one pass "
+        f"{out['one_pass_ms_per_step']:.3f} ms/step ({out['events_per_step']} events)")
+    for o in objs:
+        for h in o:
+            h.close()
+    return out
 
 
 def batched_leg(F, torch, dev, replays: int, parity: bool, rotate: int = 4):
