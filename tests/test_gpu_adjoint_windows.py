@@ -10,7 +10,8 @@ gradients must be bit-identical for every cap on windows per launch
 0 = no cap), on the tape path and on the checkpoint path, and within the
 oracle's gradient bars (1e-5 relative, as the other adjoint tests).
 Shapes: chunks of whole windows, with a partial last window, of one window
-and just over one; 24 to 1003 channels (a ragged last channel group).
+and just over one; 24 to 1003 channels (a ragged last channel group);
+cascades of 2 to 8 sections.
 """
 
 import numpy as np
@@ -102,6 +103,37 @@ def test_windows_per_launch_bit_identical(F, tape, n_ch, splits):
     assert float(np.max(np.abs(adj.T[cols] - oadj)) / np.max(np.abs(oadj))) <= 1e-6
     if len(cols) == n_ch:
         assert float(np.linalg.norm(gs - ogs) / np.linalg.norm(ogs)) <= 1e-5
+
+
+@pytest.mark.parametrize("order,btype,f1,f2,fs", [
+    (4, "lowpass", 30.0, 0.0, 200.0),       # 2 sections
+    (10, "bandpass", 2.0, 60.0, 500.0),     # 5 sections: level matrices read from LDS
+    (16, "bandpass", 5.0, 400.0, 2000.0),   # 8 sections
+])
+def test_windows_per_launch_other_orders(F, order, btype, f1, f2, fs):
+    """The several-window kernel for the other section counts it is built
+    for: bit for bit against one launch per window, and the oracle's bars."""
+    orc = _orc()
+    sos = orc.butter_sos(order, btype, f1, f2, fs)
+    n_ch, nsta, nlta = 29, 15, 150
+    splits = [(0, 3 * 512 + 100)]
+    n_t = splits[-1][1]
+    g = torch.Generator(device="cuda").manual_seed(order)
+    x = torch.randn((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32)
+    tgt = torch.rand((n_t, n_ch), generator=g, device="cuda", dtype=torch.float32) * 3.0
+    scale = 1.0 / x.numel()
+    for tape in (True, False):
+        ref = _adjoint(F, sos, x, tgt, nsta, nlta, "mse", scale, tape, 1, splits)
+        got = _adjoint(F, sos, x, tgt, nsta, nlta, "mse", scale, tape, 0, splits)
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
+    gx, adj, gs = ref
+    xh = x.cpu().numpy().astype(np.float64)
+    th = tgt.cpu().numpy().astype(np.float64)
+    _, ogx, ogs, oadj = orc.stalta_grad(sos, xh, th, nsta, nlta, scale)
+    assert max_rel_rms(gx, ogx) <= 1e-5
+    assert float(np.linalg.norm(gs - ogs) / np.linalg.norm(ogs)) <= 1e-5
+    assert float(np.max(np.abs(adj.T - oadj)) / np.max(np.abs(oadj))) <= 1e-6
 
 
 def test_windows_per_launch_grad_mode(F):
