@@ -769,7 +769,7 @@ def batched_leg(F, torch, dev, replays: int, parity: bool, rotate: int = 4):
                 "algorithmic_gbs": achieved,
                 "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": achieved / HBM_PEAK_GBS, "traffic": batch_traffic,
-                             "kernel": "fwd_batch_kernel<KMAX=5> (persistent; one reset kernel beside it)",
+                             "kernel": "fwd_batch_kernel<KMAX=5> (persistent; the launch's only kernel)",
                              "algorithmic_bytes_per_launch": bytes_launch,
                              "working_set_bytes": rotate * bytes_launch},
                 "latency_us": [{"p50": float(np.percentile(lat[:, i], 50)), "p90": float(np.percentile(lat[:, i], 90)),

@@ -197,8 +197,8 @@ hipError_t launch_fwd_l64(const FwdParams &p, int K, bool stalta, bool write_y, 
 hipError_t launch_fwd(const FwdParams &p, int K, int L, bool stalta, bool write_y, bool unit, bool rev,
                       hipStream_t stream);
 
-// Batched launch: the reset kernel (queue counters and stamps) and the
-// persistent kernel, grid workgroups of nw waves with lds bytes of dynamic
+// Batched launch: the persistent kernel (it leaves the queue counters cleared
+// for the next launch), grid workgroups of nw waves with lds bytes of dynamic
 // LDS, for cascades of up to kmax sections and 48-row blocks.  The occupancy
 // query gives the workgroups of that kernel resident per CU.
 hipError_t launch_fwd_batch(const BatchParams &bp, int kmax, int grid, int nw, size_t lds, hipStream_t stream);
