@@ -48,8 +48,10 @@ __device__ __forceinline__ void trig_window(tparams_t p, int g, const float (&xv
   const float on = p->on, off = p->off;
 
   // the carried state of the channel: read by the lanes of block 0 and
-  // staged in LDS; the barrier below also waits for these reads, so the
-  // write-back after the scan cannot overtake them
+  // staged in LDS (the LDS writes wait for the reads' data, so the
+  // write-back after the scan cannot overtake them).  The barriers here are
+  // LDS-only: the window's own loads and stores (the cf rows of the
+  // standalone kernel, the fused launch's y and cf stores) stay in flight.
   if (threadIdx.x == 0) wg_cnt = 0u;
   if (b == 0) {
     s_x[cl] = cval && p->open[c] ? -2 : -1;
@@ -57,7 +59,7 @@ __device__ __forceinline__ void trig_window(tparams_t p, int g, const float (&xv
     g0_x[cl] = cval ? p->cnt[c] : 0;
   }
 
-  __syncthreads();  // workgroup barrier with every wave's memory reads complete
+  lds_barrier();
   const int s_in = s_x[cl];
   const int64_t ton_in = ton_x[cl], g0 = g0_x[cl];
 
@@ -105,12 +107,12 @@ __device__ __forceinline__ void trig_window(tparams_t p, int g, const float (&xv
   // events closing in this block, and their slots within the workgroup
   const int n_ev = cval ? (s == -1 ? ca : cb) : 0;
   const unsigned int mine = n_ev > 0 ? atomicAdd(&wg_cnt, (unsigned int)n_ev) : 0u;
-  __syncthreads();  // every lane's slots taken
+  lds_barrier();  // every lane's slots taken
   if (threadIdx.x == 0) {
     // one reservation per workgroup on the caller's counter
     base_x = wg_cnt > 0u ? atomicAdd(p->count, (unsigned long long)wg_cnt) : 0ull;
   }
-  __syncthreads();  // base_x
+  lds_barrier();  // base_x (written from the atomic's returned value)
   if (n_ev == 0) return;
   const int64_t cap = p->cap;
   int64_t pos = (int64_t)base_x + (int64_t)mine;
