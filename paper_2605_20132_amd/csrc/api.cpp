@@ -1097,12 +1097,12 @@ filark_status adjoint_run(filark_sos_t sos, filark_stalta_t sl, const double *ta
   p.ald = 1.0 - p.cl;
   p.nlta = sl->nlta;
   const uint64_t rowb = (uint64_t)n_ch * 4u;
-  // Full windows run several to a launch where the tile and the cascade
-  // allow (the default adjoint tile on a Butterworth-shaped cascade): the
-  // adjoint state then passes between them on chip.  The window starts are
+  // The windows of a chunk run several to a launch where the tile and the
+  // cascade allow (the default adjoint tile on a Butterworth-shaped
+  // cascade): the adjoint state then passes between them on chip.  The window starts are
   // addressed as evenly spaced slots, so on the checkpoint path slot 0 gets
   // a copy of the objects' state.
-  const bool multi = adj_multi_fits(ta.waves, ta.group, ta.block, ta.levels()) && K >= 2 &&
+  const bool multi = adj_multi_fits(ta.waves, ta.group, ta.block, ta.levels()) && K >= 2 && K <= kMultiMaxSections &&
                      sos->cas.unit_tail() && p.recon == 1 && sos->adj_windows != 1;
   const int64_t cap = sos->adj_windows > 0 ? sos->adj_windows : n_win;
   if (multi && !tape && e == hipSuccess && n_win > 1) e = seed(0, 0);
@@ -1110,15 +1110,18 @@ filark_status adjoint_run(filark_sos_t sos, filark_stalta_t sl, const double *ta
   p.ck_stride = (int64_t)ck_doubles;
   for (int64_t w = n_win - 1; w >= 0 && e == hipSuccess;) {
     const int64_t nt = std::min(rows, n_t - w * rows);
-    // windows w_lo .. w in this launch, last to first
-    const int64_t w_lo = (multi && nt == rows) ? std::max<int64_t>(0, w - cap + 1) : w;
+    // windows w_lo .. w in this launch, last to first; only the chunk's last
+    // window (w, taken first) may be partial
+    const int64_t w_lo = multi ? std::max<int64_t>(0, w - cap + 1) : w;
     const size_t off = (size_t)(w_lo * rows) * (size_t)n_ch;
     p.x = x + off;
     p.g = g + off;
     p.gx = gx + off;
-    p.n_t = (int32_t)nt;
     p.n_win = (int32_t)(w - w_lo + 1);
-    p.range = (int32_t)((uint64_t)nt * rowb);
+    p.n_t = (int32_t)(p.n_win > 1 ? rows : nt);
+    p.range = (int32_t)((uint64_t)p.n_t * rowb);
+    p.n_t_last = (int32_t)nt;
+    p.range_last = (int32_t)((uint64_t)nt * rowb);
     if (tape) {
       const double *slot = tape + (size_t)w_lo * ck_doubles;
       p.zs0 = slot;

@@ -87,13 +87,16 @@ struct AdjParams {
   double asd, ald;     // 1 - 1/nsta, 1 - 1/nlta
   double cs, cl;       // 1/nsta, 1/nlta
   int64_t nlta;
-  // several full windows in one launch (n_win > 1, default adjoint tile
-  // only): x, g, gx, zs0, sl0, cnt0 and `range` describe the launch's first
-  // window; window i is offset by i * win_elems elements of x, g, gx and by
+  // several windows in one launch (n_win > 1, default adjoint tile only):
+  // x, g, gx, zs0, sl0, cnt0, n_t and `range` describe the launch's first
+  // window (a full one); window i is offset by i * win_elems elements of x, g, gx and by
   // i * ck_stride doubles of the start-state slots (zs0, sl0, cnt0 alike)
   int32_t n_win;
   int64_t win_elems;
   int64_t ck_stride;
+  // rows and buffer range of the launch's last window: n_t and range for a
+  // launch of full windows, fewer for a chunk's partial last window
+  int32_t n_t_last, range_last;
 };
 
 // The several-window adjoint kernel runs the default adjoint tile only
@@ -104,6 +107,9 @@ constexpr int kMultiWaves = 4;
 constexpr int kMultiGroup = 8;
 constexpr int kMultiCwLog2 = 3;
 constexpr int kMultiLevels = 5;
+// Cascades of more sections spill registers in that kernel (and so run one
+// launch per window).
+constexpr int kMultiMaxSections = 4;
 inline bool adj_multi_fits(int nw, int cw, int L, int n_lev) {
   return L == 16 && nw == kMultiWaves && cw == kMultiGroup && n_lev == kMultiLevels;
 }

@@ -11,7 +11,7 @@ gradients must be bit-identical for every cap on windows per launch
 oracle's gradient bars (1e-5 relative, as the other adjoint tests).
 Shapes: chunks of whole windows, with a partial last window, of one window
 and just over one; 24 to 1003 channels (a ragged last channel group);
-cascades of 2 to 8 sections.
+cascades of 2 to 8 sections (the several-window kernel takes 2 to 4).
 """
 
 import numpy as np
@@ -107,12 +107,14 @@ def test_windows_per_launch_bit_identical(F, tape, n_ch, splits):
 
 @pytest.mark.parametrize("order,btype,f1,f2,fs", [
     (4, "lowpass", 30.0, 0.0, 200.0),       # 2 sections
-    (10, "bandpass", 2.0, 60.0, 500.0),     # 5 sections: level matrices read from LDS
-    (16, "bandpass", 5.0, 400.0, 2000.0),   # 8 sections
+    (6, "bandpass", 2.0, 60.0, 500.0),      # 3 sections
+    (10, "bandpass", 2.0, 60.0, 500.0),     # 5 sections: one launch per window (the cap is moot)
+    (16, "bandpass", 5.0, 400.0, 2000.0),   # 8 sections: likewise
 ])
 def test_windows_per_launch_other_orders(F, order, btype, f1, f2, fs):
     """The several-window kernel for the other section counts it is built
-    for: bit for bit against one launch per window, and the oracle's bars."""
+    for (2 to 4; longer cascades run one launch per window): bit for bit
+    against one launch per window, and the oracle's bars."""
     orc = _orc()
     sos = orc.butter_sos(order, btype, f1, f2, fs)
     n_ch, nsta, nlta = 29, 15, 150
