@@ -224,11 +224,12 @@ filark_status filark_tile_get(const void *st, int kind, int *block, int *waves, 
 /*
  * Most adjoint windows that one launch of the adjoint kernel takes (0, the
  * default: no limit; 1: one launch per window).  With the default adjoint
- * tile and a cascade whose sections after the first have numerators
- * [1, +-2, 1] and |a2| >= 1/4 (every Butterworth design), the full windows
- * of a chunk run in one launch: each workgroup keeps its channels from
- * window to window, hands the adjoint state on through LDS and loads the
- * next window's input while the current one runs.  Results are bit-identical
+ * tile and a cascade of 2 to 4 sections whose sections after the first
+ * have numerators [1, +-2, 1] and |a2| >= 1/4 (every even-order Butterworth
+ * design), all windows of a chunk run in one launch, a partial last window
+ * first: each workgroup keeps its channels from window to window,
+ * hands the adjoint state on through LDS and loads the next window's input
+ * while the current one runs.  Other cascades take one launch per window.  Results are bit-identical
  * for every value (the windows' arithmetic and its order do not change); the
  * limit exists to measure and test that.  Takes effect at the next adjoint
  * call.  FILARK_EINVAL for a null state or a negative value.
