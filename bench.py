@@ -41,21 +41,35 @@ def log(*a):
 # checks, input generation) the GPU comes back at idle clocks and needs
 # 10-15 steps (~30 ms) of the plain forward to reach its steady rate
 # (2.18 -> 2.00 -> 1.94 -> 1.93 ms per step in blocks of 5 steps after 3 s
-# idle).  0 under --profile, whose kernel traces hold exactly the warm-up
-# and timed launches.
+# idle).  Under --profile the ramp runs a plain device fill instead, so that
+# kernel traces hold exactly the warm-up and timed launches of each leg.
 RAMP_S = 0.1
+RAMP_WITH_FILL = False
+_fill_buf = []
+
+
+def ramp(torch, fn, *a) -> int:
+    """RAMP_S seconds of wall time of calls of fn (of device fills under
+    --profile), each synchronised; returns the number of calls of fn."""
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < RAMP_S:
+        if RAMP_WITH_FILL:
+            if not _fill_buf:
+                _fill_buf.append(torch.empty(64 << 20, dtype=torch.float32, device="cuda"))
+            _fill_buf[0].fill_(1.0)
+        else:
+            fn(*a)
+            n += 1
+        torch.cuda.synchronize()
+    return n
 
 
 def warm(torch, fn, *a) -> int:
-    """One call of fn, then more until RAMP_S seconds of wall time have
-    passed, each synchronised; returns the number of calls."""
-    n, t0 = 0, time.perf_counter()
-    while True:
-        fn(*a)
-        torch.cuda.synchronize()
-        n += 1
-        if time.perf_counter() - t0 >= RAMP_S:
-            return n
+    """One warm-up call of fn, then the clock ramp; returns the number of
+    calls of fn beyond the first."""
+    fn(*a)
+    torch.cuda.synchronize()
+    return ramp(torch, fn, *a)
 
 
 def kernel_hash(sources) -> str:
@@ -936,8 +950,8 @@ def main():
                     help="also run one plain device copy of 512 MiB (counter calibration for profiles)")
     args = ap.parse_args()
     if args.profile:
-        global RAMP_S
-        RAMP_S = 0.0
+        global RAMP_WITH_FILL
+        RAMP_WITH_FILL = True
         args.no_parity = True
         args.no_cpu = True
     if args.gpus != 1:
@@ -1010,7 +1024,7 @@ def main():
             f"cf {parity['max_rel_rms_cf']:.2e}")
 
     # ---- clock ramp (RAMP_S): untimed steps before the warm-up steps proper
-    ramp = warm(torch, step, st, sl) if RAMP_S > 0 else 0
+    ramp_steps = ramp(torch, step, st, sl)
 
     # ---- timed steps (states continue across steps: a continuous stream)
     for _ in range(args.warmup):
@@ -1109,7 +1123,7 @@ def main():
 
     out = {
         "metric": METRIC, "value": value, "unit": "channel-samples/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "clock_ramp_steps": ramp, "ms_per_step": ms_step, "higher_is_better": True,
+        "steps": args.steps, "warmup": args.warmup, "clock_ramp_steps": ramp_steps, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"plain forward: {n_ch} ch x {n_t} samples FP32 @ {w.fs:g} Hz in "
                                f"{n_chunks} chunks of {chunk}; Butterworth BP order {w.order} "
